@@ -1,0 +1,464 @@
+// ADMM-on-a-factor-graph oracle: plain, serial, double precision.
+//
+// TEST INFRASTRUCTURE ONLY.  This file is the slow, obviously-correct
+// reference that the HIP library is checked against.  Only the tests, the
+// smoke check and the CPU-baseline leg of the benchmark may load it; the
+// product path never does.  It shares no code, header, table or helper
+// with the GPU library.
+//
+// What it computes (paper Sec. II, Algorithm 2, and eq. (3) for the
+// proximal operator):
+//   repeat
+//     x-update: for every factor a, x_(a,.) = Prox_{f_a,rho}(n_(a,.))
+//     m-update: m_e = x_e + u_e                      for every edge e
+//     z-update: z_b = sum_{a in db} rho m_(a,b) / sum_{a in db} rho
+//     u-update: u_e = u_e + alpha (x_e - z_b)
+//     n-update: n_e = z_b - u_e
+// Each update is its own loop over factors, edges or variables, in the
+// paper's order, summing in edge-creation order.  rho and alpha are one
+// value for all edges.
+//
+// Proximal operators (paper appendix, with the readings listed in the
+// design notes):
+//   nonoverlap  (App. A, first PO)  projection onto |c1-c2| >= r1+r2; the
+//               radii move by -D/4 (the printed +1 radius direction leaves
+//               the pair overlapping); n_hat = (1,0) when the centres meet.
+//   wall        (App. A, second PO) projection onto Q^T(c-V) >= r, general
+//               |Q|.
+//   radius      (App. A, third PO)  argmin -gamma/2 r^2 + rho/2 (r-n)^2 over
+//               r >= 0, which needs rho > gamma.
+//   quad        (App. B, cost PO)   f = 1/2 sum_k q_k x_k^2.
+//   lindyn(0)   (App. B, dynamics PO) projection onto x' = A x + B u
+//               (x fixed to the parameter x0 for the first step), solved
+//               from its normal equations with Gaussian elimination.
+//   box         clip to [lo, hi] per component.
+//   hinge       f = C max(0, 1 - y(w.a + b)), the minimal-error and margin
+//               POs of App. C merged into one factor per point.
+//   l2          f = lambda/2 |w|^2 (App. C, norm-two PO).
+//
+// Stopping measures (the paper leaves them open): after the u-update,
+//   r = max_e |x_e - z_b|        s = rho * max_b |z_b - z_b(previous)|.
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <vector>
+
+namespace {
+
+enum Kind {
+  K_NONOVERLAP = 1,
+  K_WALL = 2,
+  K_RADIUS = 3,
+  K_QUAD = 4,
+  K_BOX = 5,
+  K_HINGE = 6,
+  K_L2 = 7,
+  K_LINDYN = 8,
+  K_LINDYN0 = 9,
+};
+
+struct Factor {
+  int kind;
+  std::vector<int> vars;     // variable id of each edge, in edge order
+  std::vector<long> slot;    // first slot of each edge in the edge arrays
+  int nslots;                // total scalar slots of this factor
+  std::vector<double> p;     // parameters
+};
+
+struct Graph {
+  std::vector<int> dim;      // per variable
+  std::vector<long> zoff;    // per variable, offset into z
+  long nz = 0;
+  std::vector<Factor> F;
+  long nslot = 0;            // total edge slots
+  std::vector<long> slot_z;  // z index of each edge slot
+  std::vector<double> z, zprev, x, m, u, n;
+  double rho = 1.0, alpha = 1.0;
+  double r_primal = 0.0, r_dual = 0.0;
+};
+
+// ---------------------------------------------------------------------------
+// Small dense linear solve: Gaussian elimination with partial pivoting.
+// a is k x k row-major (destroyed), b is k (overwritten with the solution).
+// ---------------------------------------------------------------------------
+bool solve_dense(std::vector<double>& a, std::vector<double>& b, int k) {
+  for (int c = 0; c < k; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < k; ++r)
+      if (std::fabs(a[r * k + c]) > std::fabs(a[piv * k + c])) piv = r;
+    if (a[piv * k + c] == 0.0) return false;
+    if (piv != c) {
+      for (int j = 0; j < k; ++j) std::swap(a[c * k + j], a[piv * k + j]);
+      std::swap(b[c], b[piv]);
+    }
+    for (int r = c + 1; r < k; ++r) {
+      double f = a[r * k + c] / a[c * k + c];
+      if (f == 0.0) continue;
+      for (int j = c; j < k; ++j) a[r * k + j] -= f * a[c * k + j];
+      b[r] -= f * b[c];
+    }
+  }
+  for (int r = k - 1; r >= 0; --r) {
+    double s = b[r];
+    for (int j = r + 1; j < k; ++j) s -= a[r * k + j] * b[j];
+    b[r] = s / a[r * k + r];
+  }
+  return true;
+}
+
+// ---------------------------------------------------------------------------
+// Proximal operators.  nv: the factor's n vector (its edges' slots
+// concatenated), out: x for the same slots.  dims: dimension of each edge.
+// ---------------------------------------------------------------------------
+
+// |c1 - c2| >= r1 + r2 on edges (c1, r1, c2, r2).
+void prox_nonoverlap(const double* nv, double rho, double* out) {
+  (void)rho;  // equal weights on all four edges: the step does not depend on rho
+  const double c1x = nv[0], c1y = nv[1], r1 = nv[2];
+  const double c2x = nv[3], c2y = nv[4], r2 = nv[5];
+  const double dx = c2x - c1x, dy = c2y - c1y;
+  const double L = std::sqrt(dx * dx + dy * dy);
+  double hx = 1.0, hy = 0.0;
+  if (L > 0.0) { hx = dx / L; hy = dy / L; }
+  const double D = std::max(0.0, r1 + r2 - L);
+  // lambda = D / (1/rho + 1/rho + 1/rho + 1/rho); each edge moves lambda/rho.
+  const double lam = D / (4.0 / rho);
+  const double step = lam / rho;
+  out[0] = c1x - step * hx;
+  out[1] = c1y - step * hy;
+  out[2] = r1 - step;
+  out[3] = c2x + step * hx;
+  out[4] = c2y + step * hy;
+  out[5] = r2 - step;
+}
+
+// Q^T (c - V) >= r on edges (c, r); p = (Qx, Qy, Vx, Vy).
+void prox_wall(const double* nv, const double* p, double rho, double* out) {
+  const double Qx = p[0], Qy = p[1], Vx = p[2], Vy = p[3];
+  const double g = Qx * (nv[0] - Vx) + Qy * (nv[1] - Vy) - nv[2];
+  out[0] = nv[0]; out[1] = nv[1]; out[2] = nv[2];
+  if (g >= 0.0) return;
+  const double lam = -g / ((Qx * Qx + Qy * Qy) / rho + 1.0 / rho);
+  out[0] = nv[0] + (lam / rho) * Qx;
+  out[1] = nv[1] + (lam / rho) * Qy;
+  out[2] = nv[2] - lam / rho;
+}
+
+// argmin_{r >= 0} -gamma/2 r^2 + rho/2 (r - n)^2.
+void prox_radius(const double* nv, double gamma, double rho, double* out) {
+  out[0] = std::max(0.0, rho * nv[0] / (rho - gamma));
+}
+
+// f = 1/2 sum q_k x_k^2.
+void prox_quad(const double* nv, int k, const double* q, double rho, double* out) {
+  for (int i = 0; i < k; ++i) out[i] = rho * nv[i] / (rho + q[i]);
+}
+
+void prox_box(const double* nv, int k, double lo, double hi, double* out) {
+  for (int i = 0; i < k; ++i) out[i] = std::min(hi, std::max(lo, nv[i]));
+}
+
+// f = C max(0, 1 - y (w.a + b)) on scalar edges (w_1..w_d, b);
+// p = (a_1..a_d, y, C).
+void prox_hinge(const double* nv, int d, const double* p, double rho, double* out) {
+  const double y = p[d], C = p[d + 1];
+  double s = nv[d];
+  double aa = 0.0;
+  for (int k = 0; k < d; ++k) { s += nv[k] * p[k]; aa += p[k] * p[k]; }
+  s *= y;
+  const double D = aa / rho + 1.0 / rho;
+  const double tau = std::min(C, std::max(0.0, (1.0 - s) / D));
+  for (int k = 0; k < d; ++k) out[k] = nv[k] + tau * y * p[k] / rho;
+  out[d] = nv[d] + tau * y / rho;
+}
+
+// f = lam/2 |w|^2.
+void prox_l2(const double* nv, int k, double lam, double rho, double* out) {
+  for (int i = 0; i < k; ++i) out[i] = rho * nv[i] / (rho + lam);
+}
+
+// Projection onto x' = A x + B u on edges (x, u, x') with A n x n, B n x m
+// (row-major).  Minimise |a - a_n|^2 + |M a - b|^2 with a = (x, u),
+// M = [A B], b = n_x': normal equations (I + M^T M) a = a_n + M^T b.
+void prox_lindyn(const double* nv, int n, int m, const double* A,
+                 const double* B, double* out) {
+  const int k = n + m;
+  std::vector<double> M(static_cast<size_t>(n) * k);
+  for (int i = 0; i < n; ++i) {
+    for (int j = 0; j < n; ++j) M[i * k + j] = A[i * n + j];
+    for (int j = 0; j < m; ++j) M[i * k + n + j] = B[i * m + j];
+  }
+  const double* an = nv;
+  const double* b = nv + k;
+  std::vector<double> H(static_cast<size_t>(k) * k, 0.0), rhs(k);
+  for (int i = 0; i < k; ++i) {
+    H[i * k + i] = 1.0;
+    double s = an[i];
+    for (int r = 0; r < n; ++r) s += M[r * k + i] * b[r];
+    rhs[i] = s;
+    for (int j = 0; j < k; ++j) {
+      double h = 0.0;
+      for (int r = 0; r < n; ++r) h += M[r * k + i] * M[r * k + j];
+      H[i * k + j] += h;
+    }
+  }
+  solve_dense(H, rhs, k);
+  for (int i = 0; i < k; ++i) out[i] = rhs[i];
+  for (int r = 0; r < n; ++r) {
+    double s = 0.0;
+    for (int j = 0; j < k; ++j) s += M[r * k + j] * rhs[j];
+    out[k + r] = s;
+  }
+}
+
+// First step: x1 = A x0 + B u0 with x0 a parameter; edges (u0, x1).
+void prox_lindyn0(const double* nv, int n, int m, const double* A,
+                  const double* B, const double* x0, double* out) {
+  std::vector<double> c(n);
+  for (int r = 0; r < n; ++r) {
+    double s = 0.0;
+    for (int j = 0; j < n; ++j) s += A[r * n + j] * x0[j];
+    c[r] = s;
+  }
+  const double* nu = nv;
+  const double* b = nv + m;
+  // minimise |u - n_u|^2 + |B u + c - b|^2:  (I + B^T B) u = n_u + B^T (b - c)
+  std::vector<double> H(static_cast<size_t>(m) * m, 0.0), rhs(m);
+  for (int i = 0; i < m; ++i) {
+    H[i * m + i] = 1.0;
+    double s = nu[i];
+    for (int r = 0; r < n; ++r) s += B[r * m + i] * (b[r] - c[r]);
+    rhs[i] = s;
+    for (int j = 0; j < m; ++j) {
+      double h = 0.0;
+      for (int r = 0; r < n; ++r) h += B[r * m + i] * B[r * m + j];
+      H[i * m + j] += h;
+    }
+  }
+  solve_dense(H, rhs, m);
+  for (int i = 0; i < m; ++i) out[i] = rhs[i];
+  for (int r = 0; r < n; ++r) {
+    double s = c[r];
+    for (int j = 0; j < m; ++j) s += B[r * m + j] * rhs[j];
+    out[m + r] = s;
+  }
+}
+
+// Dispatch one factor.  dims: the dimension of each of its edges.
+int prox_apply(int kind, int arity, const int* dims, const double* p, int plen,
+               double rho, const double* nv, double* out) {
+  switch (kind) {
+    case K_NONOVERLAP:
+      if (arity != 4 || dims[0] != 2 || dims[1] != 1 || dims[2] != 2 || dims[3] != 1) return -1;
+      prox_nonoverlap(nv, rho, out);
+      return 0;
+    case K_WALL:
+      if (arity != 2 || dims[0] != 2 || dims[1] != 1 || plen != 4) return -1;
+      prox_wall(nv, p, rho, out);
+      return 0;
+    case K_RADIUS:
+      if (arity != 1 || dims[0] != 1 || plen != 1) return -1;
+      if (!(rho > p[0])) return -2;
+      prox_radius(nv, p[0], rho, out);
+      return 0;
+    case K_QUAD: {
+      int k = 0;
+      for (int e = 0; e < arity; ++e) k += dims[e];
+      if (plen != k) return -1;
+      prox_quad(nv, k, p, rho, out);
+      return 0;
+    }
+    case K_BOX: {
+      int k = 0;
+      for (int e = 0; e < arity; ++e) k += dims[e];
+      if (plen != 2) return -1;
+      prox_box(nv, k, p[0], p[1], out);
+      return 0;
+    }
+    case K_HINGE: {
+      const int d = arity - 1;
+      for (int e = 0; e < arity; ++e) if (dims[e] != 1) return -1;
+      if (d < 1 || plen != d + 2) return -1;
+      prox_hinge(nv, d, p, rho, out);
+      return 0;
+    }
+    case K_L2: {
+      int k = 0;
+      for (int e = 0; e < arity; ++e) k += dims[e];
+      if (plen != 1) return -1;
+      prox_l2(nv, k, p[0], rho, out);
+      return 0;
+    }
+    case K_LINDYN: {
+      if (arity != 3 || dims[0] != dims[2]) return -1;
+      const int n = dims[0], m = dims[1];
+      if (plen != n * n + n * m) return -1;
+      prox_lindyn(nv, n, m, p, p + n * n, out);
+      return 0;
+    }
+    case K_LINDYN0: {
+      if (arity != 2) return -1;
+      const int m = dims[0], n = dims[1];
+      if (plen != n * n + n * m + n) return -1;
+      prox_lindyn0(nv, n, m, p, p + n * n, p + n * n + n * m, out);
+      return 0;
+    }
+    default:
+      return -1;
+  }
+}
+
+// One iteration of Algorithm 2, each update its own loop.
+void iterate(Graph& g) {
+  const long S = g.nslot;
+  // n-update of the previous iteration (n = z - u), kept explicit.
+  for (long e = 0; e < S; ++e) g.n[e] = g.z[g.slot_z[e]] - g.u[e];
+  // x-update.
+  std::vector<int> dims;
+  for (const Factor& f : g.F) {
+    dims.resize(f.vars.size());
+    for (size_t k = 0; k < f.vars.size(); ++k) dims[k] = g.dim[f.vars[k]];
+    const long s0 = f.slot[0];
+    prox_apply(f.kind, static_cast<int>(f.vars.size()), dims.data(),
+               f.p.data(), static_cast<int>(f.p.size()), g.rho,
+               &g.n[s0], &g.x[s0]);
+  }
+  // m-update.
+  for (long e = 0; e < S; ++e) g.m[e] = g.x[e] + g.u[e];
+  // z-update: sum in edge-creation order; a variable with no edge keeps z.
+  g.zprev = g.z;
+  std::vector<double> num(g.nz, 0.0), den(g.nz, 0.0);
+  for (long e = 0; e < S; ++e) {
+    num[g.slot_z[e]] += g.rho * g.m[e];
+    den[g.slot_z[e]] += g.rho;
+  }
+  for (long b = 0; b < g.nz; ++b)
+    if (den[b] > 0.0) g.z[b] = num[b] / den[b];
+  // u-update.
+  for (long e = 0; e < S; ++e) g.u[e] += g.alpha * (g.x[e] - g.z[g.slot_z[e]]);
+  // Stopping measures.
+  double r = 0.0, s = 0.0;
+  for (long e = 0; e < S; ++e) r = std::max(r, std::fabs(g.x[e] - g.z[g.slot_z[e]]));
+  for (long b = 0; b < g.nz; ++b) s = std::max(s, std::fabs(g.z[b] - g.zprev[b]));
+  g.r_primal = r;
+  g.r_dual = g.rho * s;
+}
+
+}  // namespace
+
+extern "C" {
+
+void* orc_graph_create(int n_vars, const int* dims) {
+  Graph* g = new Graph();
+  g->dim.assign(dims, dims + n_vars);
+  g->zoff.resize(n_vars);
+  long off = 0;
+  for (int i = 0; i < n_vars; ++i) { g->zoff[i] = off; off += dims[i]; }
+  g->nz = off;
+  g->z.assign(off, 0.0);
+  g->zprev.assign(off, 0.0);
+  return g;
+}
+
+void orc_graph_destroy(void* h) { delete static_cast<Graph*>(h); }
+
+// Append one factor; returns 0 or -1 on a bad variable id.
+int orc_add_factor(void* h, int kind, int arity, const int* vars,
+                   const double* params, int plen) {
+  Graph* g = static_cast<Graph*>(h);
+  Factor f;
+  f.kind = kind;
+  f.nslots = 0;
+  for (int k = 0; k < arity; ++k) {
+    if (vars[k] < 0 || vars[k] >= static_cast<int>(g->dim.size())) return -1;
+    f.vars.push_back(vars[k]);
+    f.slot.push_back(g->nslot + f.nslots);
+    for (int c = 0; c < g->dim[vars[k]]; ++c)
+      g->slot_z.push_back(g->zoff[vars[k]] + c);
+    f.nslots += g->dim[vars[k]];
+  }
+  f.p.assign(params, params + plen);
+  g->nslot += f.nslots;
+  g->F.push_back(std::move(f));
+  return 0;
+}
+
+// Add n factors of one kind; vars [n*arity]; params [n*plen] or, when
+// shared != 0, [plen] for all.
+int orc_add_factors(void* h, int kind, int n, int arity, const int* vars,
+                    const double* params, int plen, int shared) {
+  for (int i = 0; i < n; ++i) {
+    const double* p = shared ? params : params + static_cast<long>(i) * plen;
+    int rc = orc_add_factor(h, kind, arity, vars + static_cast<long>(i) * arity, p, plen);
+    if (rc) return rc;
+  }
+  return 0;
+}
+
+void orc_set_params(void* h, double rho, double alpha) {
+  Graph* g = static_cast<Graph*>(h);
+  g->rho = rho;
+  g->alpha = alpha;
+}
+
+long orc_num_slots(void* h) { return static_cast<Graph*>(h)->nslot; }
+long orc_num_z(void* h) { return static_cast<Graph*>(h)->nz; }
+
+// Initial state: z given, u = 0 (or given per edge slot when u != null).
+void orc_set_state(void* h, const double* z, const double* u) {
+  Graph* g = static_cast<Graph*>(h);
+  std::memcpy(g->z.data(), z, sizeof(double) * g->nz);
+  g->u.assign(g->nslot, 0.0);
+  if (u) std::memcpy(g->u.data(), u, sizeof(double) * g->nslot);
+  g->x.assign(g->nslot, 0.0);
+  g->m.assign(g->nslot, 0.0);
+  g->n.assign(g->nslot, 0.0);
+}
+
+// Run up to max_iter iterations; when tol > 0 stop at the first iteration
+// whose r and s are both <= tol.  Returns the iterations done.
+int orc_run(void* h, int max_iter, double tol) {
+  Graph* g = static_cast<Graph*>(h);
+  if (static_cast<long>(g->u.size()) != g->nslot) orc_set_state(h, g->z.data(), nullptr);
+  for (int k = 1; k <= max_iter; ++k) {
+    iterate(*g);
+    if (tol > 0.0 && g->r_primal <= tol && g->r_dual <= tol) return k;
+  }
+  return max_iter;
+}
+
+void orc_get_z(void* h, double* z) {
+  Graph* g = static_cast<Graph*>(h);
+  std::memcpy(z, g->z.data(), sizeof(double) * g->nz);
+}
+void orc_get_u(void* h, double* u) {
+  Graph* g = static_cast<Graph*>(h);
+  std::memcpy(u, g->u.data(), sizeof(double) * g->nslot);
+}
+void orc_get_x(void* h, double* x) {
+  Graph* g = static_cast<Graph*>(h);
+  std::memcpy(x, g->x.data(), sizeof(double) * g->nslot);
+}
+void orc_get_m(void* h, double* m) {
+  Graph* g = static_cast<Graph*>(h);
+  std::memcpy(m, g->m.data(), sizeof(double) * g->nslot);
+}
+void orc_get_slot_z(void* h, long* idx) {
+  Graph* g = static_cast<Graph*>(h);
+  std::memcpy(idx, g->slot_z.data(), sizeof(long) * g->nslot);
+}
+void orc_residuals(void* h, double* r, double* s) {
+  Graph* g = static_cast<Graph*>(h);
+  *r = g->r_primal;
+  *s = g->r_dual;
+}
+
+// A single proximal operator, for the tests that pin each one.
+int orc_prox(int kind, int arity, const int* dims, const double* params,
+             int plen, double rho, const double* nv, double* out) {
+  return prox_apply(kind, arity, dims, params, plen, rho, nv, out);
+}
+
+}  // extern "C"

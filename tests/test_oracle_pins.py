@@ -1,0 +1,144 @@
+"""Integration pins for the oracle's Algorithm 2 (paper Sec. II).
+
+* packing: one disk converges to the incircle (closed form); small packings
+  end feasible; the graph has the paper's edge/factor/node counts;
+* the z-update is the average of incoming m and, with u^0 = 0, the duals
+  around every variable sum to zero at every iteration (follows from the
+  z- and u-updates of Algorithm 2);
+* MPC without the box equals the Riccati LQR solution; with the box it
+  satisfies the active-set KKT conditions;
+* tiny SVMs satisfy the KKT conditions with the duals recovered from u and
+  match scipy's solution of the primal QP;
+* the Fig. 1 example keeps the paper's edge order.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from tests import pins
+
+
+def test_single_disk_incircle_triangle_and_square():
+    p = W.packing(1, "triangle", 0.1, seed=3)
+    g = O.OracleGraph(p)
+    g.run(3000)
+    np.testing.assert_allclose(g.z, [0.5, np.sqrt(3) / 6, np.sqrt(3) / 6], atol=1e-12)
+    p = W.packing(1, "square", 0.1, seed=4)
+    g = O.OracleGraph(p)
+    g.run(3000)
+    np.testing.assert_allclose(g.z, [0.5, 0.5, 0.5], atol=1e-12)
+
+
+@pytest.mark.parametrize("N,S,shape", [(10, 3, "triangle"), (7, 4, "square"),
+                                      (2000, 4, "square")])
+def test_packing_graph_counts(N, S, shape):
+    p = W.packing(N, shape, 0.02, seed=1)
+    c = W.packing_counts(N, S)
+    assert p.n_edges == c["edges"]
+    assert p.n_factors == c["factors"]
+    assert p.n_vars == c["var_nodes"]
+
+
+def _check_invariants(problem, iters, alpha=None):
+    g = O.OracleGraph(problem, alpha=alpha)
+    sz = g.slot_z
+    deg = np.bincount(sz, minlength=g.n_z).astype(float)
+    for _ in range(iters):
+        g.run(1)
+        m, u, z = g.m, g.u, g.z
+        zsum = np.bincount(sz, weights=m, minlength=g.n_z)
+        np.testing.assert_allclose(z[deg > 0], (zsum / np.maximum(deg, 1))[deg > 0],
+                                   rtol=1e-12, atol=1e-14)
+        usum = np.bincount(sz, weights=u, minlength=g.n_z)
+        assert np.max(np.abs(usum)) < 1e-12
+        np.testing.assert_allclose(m, g.x + (u - (1.0 if alpha is None else alpha)
+                                             * (g.x - z[sz])), atol=1e-13)
+
+
+@pytest.mark.parametrize("alpha", [None, 1.5, 0.7])
+def test_z_is_mean_of_m_and_duals_sum_to_zero(alpha):
+    _check_invariants(W.packing(6, "triangle", 0.1, seed=21), 40, alpha)
+    _check_invariants(W.svm(12, 3, seed=22), 20, alpha)
+
+
+def test_small_packing_converges_feasible():
+    p = W.workload("packing_tri10")
+    g = O.OracleGraph(p)
+    g.run(20000)
+    obj = O.packing_objective(p, g.z)
+    assert obj["max_violation"] < 1e-6
+    r, s = g.residuals()
+    assert r < 1e-6 and s < 1e-6
+    # covers a substantial part of the triangle (area sqrt(3)/4)
+    assert obj["area"] / (np.sqrt(3) / 4) > 0.7
+
+
+@pytest.mark.parametrize("T,n,m,seed", [(12, 4, 2, 1), (25, 6, 3, 2), (8, 12, 4, 3)])
+def test_unconstrained_mpc_equals_riccati(T, n, m, seed):
+    rng = np.random.default_rng(seed)
+    A, B = W.mpc_system(rng, n, m)
+    inst = W.MPCInstance(T, n, m, A, B, rng.standard_normal(n),
+                         np.ones(n), np.full(m, 0.1), u_box=0.0)
+    g = O.OracleGraph(W.mpc_graph(inst, box=False))
+    g.run(20000, tol=1e-12)
+    np.testing.assert_allclose(g.z, pins.riccati_lqr(inst), atol=1e-8)
+
+
+@pytest.mark.parametrize("seed", [5, 6, 7])
+def test_boxed_mpc_satisfies_active_set_kkt(seed):
+    rng = np.random.default_rng(seed)
+    n, m, T = 4, 2, 15
+    A, B = W.mpc_system(rng, n, m)
+    inst = W.MPCInstance(T, n, m, A, B, 3.0 * rng.standard_normal(n),
+                         np.ones(n), np.full(m, 0.1), u_box=0.5)
+    g = O.OracleGraph(W.mpc_graph(inst))
+    g.run(50000, tol=1e-12)
+    z = g.z
+    y, sign_bad, margin = pins.mpc_active_set_kkt(inst, z)
+    assert np.max(np.abs(np.abs(z[[t * (n + m) + j for t in range(T) for j in range(m)]]))) > 0.5 - 1e-9
+    np.testing.assert_allclose(z, y, atol=1e-8)
+    assert sign_bad < 1e-8
+    assert margin > -1e-9
+    o = O.mpc_objective(inst, z)
+    assert o["dyn_violation"] < 1e-8 and o["box_violation"] < 1e-10
+
+
+@pytest.mark.parametrize("N,d,seed", [(8, 2, 31), (6, 3, 32), (10, 2, 33)])
+def test_tiny_svm_kkt_and_qp(N, d, seed):
+    p = W.svm(N, d, seed=seed, sep=1.0)
+    g = O.OracleGraph(p)
+    g.run(200000, tol=1e-13)
+    z = g.z
+    w, b = z[:d], z[d]
+    a, y, C = p.meta["a"], p.meta["y"], p.meta["C"]
+    # duals from the hinge factors' b-edge: beta_i = rho y_i u_(i,b)
+    u = g.u.reshape(-1)[: N * (d + 1)].reshape(N, d + 1)
+    beta = p.rho * y * u[:, d]
+    assert np.all(beta > -1e-8) and np.all(beta < C + 1e-8)
+    np.testing.assert_allclose(w, (beta * y) @ a, atol=1e-7)
+    assert abs(np.sum(beta * y)) < 1e-7
+    margin = y * (a @ w + b)
+    for bi, mi in zip(beta, margin):
+        if bi < 1e-6:
+            assert mi > 1 - 1e-6
+        elif bi > C - 1e-6:
+            assert mi < 1 + 1e-6
+        else:
+            assert abs(mi - 1) < 1e-6
+    w_ref, b_ref, f_ref = pins.svm_primal_slsqp(a, y, C)
+    assert O.svm_objective(p, z) <= f_ref + 1e-7
+    np.testing.assert_allclose(w, w_ref, atol=1e-5)
+
+
+def test_fig1_edge_order():
+    """Edge arrays follow edge creation: for f1(w1,w2,w3) + f2(w1,w4,w5) +
+    f3(w2,w5) + f4(w5) the order is (1,1),(1,2),(1,3),(2,1),(2,4),(2,5),
+    (3,2),(3,5),(4,5); z has one entry per variable (five)."""
+    facs = W.fig1_topology()
+    groups = [W.FactorGroup("l2", np.array([f], np.int32), np.array([1.0]), True)
+              for f in facs]
+    p = W.Problem("fig1", np.ones(5, np.int32), groups, np.arange(5.0))
+    g = O.OracleGraph(p)
+    np.testing.assert_array_equal(g.slot_z, [0, 1, 2, 0, 3, 4, 1, 4, 4])
+    assert g.n_z == 5
