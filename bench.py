@@ -1,0 +1,175 @@
+"""Benchmark: factor-graph ADMM on one MI355X.
+
+Workload: circle packing, 2000 disks in the unit square (1,999,000 pairwise
+non-overlap factors, 4 wall factors and 1 radius factor per disk:
+8,014,000 edges, 12,020,000 edge slots), rho = 1, alpha = 1, FP32.  One
+step = one full solve of 1000 iterations of Algorithm 2 on the GPU-resident
+graph.  value = edges x iterations / second (edge-updates/s).
+
+Also printed on the same JSON line:
+  roofline      the x-pass kernel (the dominant kernel): algorithmic bytes
+                per launch / its average duration from HIP events recorded
+                on the launch stream, against 8 TB/s HBM; traffic from the
+                committed rocprofv3 counter summary when it matches the
+                current kernel source, else null;
+  cpu_baseline  the FP64 oracle on this host's CPU, one core, on a bounded
+                sample (100 iterations of the same graph by default);
+  secondary     the other workloads measured the same way (10-disk
+                triangle, 100k-point SVM).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCES = ["paper_1603_02526_amd/csrc/graph_kernels.h",
+                  "paper_1603_02526_amd/csrc/internal.h"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "xpass_packing_sq2000_traffic.json")
+
+
+def kernel_sha() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def committed_traffic():
+    """HBM bytes per x-pass launch from the committed counter summary, or
+    None when it is missing or was taken on a different kernel source."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_sha") != kernel_sha():
+        return None
+    return t.get("traffic_bytes_per_launch")
+
+
+def time_solve(g, iters, steps, warmup, torch, stream):
+    for _ in range(warmup):
+        g.run(iters, stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        g.run(iters, stream)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def cpu_baseline(problem, iters):
+    import oracle
+    o = oracle.OracleGraph(problem)
+    t0 = time.perf_counter()
+    o.run(iters)
+    dt = time.perf_counter() - t0
+    return problem.n_edges * iters / dt, dt
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--iters", type=int, default=1000, help="ADMM iterations per step")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--no-secondary", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain 512 MiB device copy (for counter scaling)")
+    ap.add_argument("--cpu-iters", type=int, default=100,
+                    help="oracle iterations in the CPU-baseline sample")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not "
+              "supported (the multi-GPU sharding is a design note only).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import workloads as W
+    from paper_1603_02526_amd import admm as A
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+
+    name = "packing_sq2000"
+    prob = W.workload(name)
+    g = A.Graph.from_problem(prob, precision=A.FP32, device=0)
+    info = g.info()
+    sec = time_solve(g, args.iters, args.steps, args.warmup, torch, stream)
+    value = prob.n_edges * args.iters / sec
+
+    # x-pass average duration from HIP events on the launch stream
+    g.set_state(prob.z0)
+    xms, zms = g.run_profiled(args.iters, stream)
+    x_avg_s = xms * 1e-3 / args.iters
+    z_avg_s = zms * 1e-3 / args.iters
+    achieved = info["algo_bytes_per_iter"] / x_avg_s / 1e9
+    traffic = committed_traffic()
+    roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS,
+                    unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4),
+                    traffic=traffic, kernel="xpass_kernel",
+                    algo_bytes_per_launch=info["algo_bytes_per_iter"],
+                    avg_launch_us=round(x_avg_s * 1e6, 3),
+                    zpass_avg_us=round(z_avg_s * 1e6, 3))
+
+    out = dict(metric="edge-updates/s", value=value, unit="edge-updates/s",
+               n_gpus=1, steps=args.steps, warmup=args.warmup,
+               ms_per_step=sec * 1e3, higher_is_better=True, scaling="weak",
+               vs_baseline=None, dtype="f32", data="synthetic",
+               config=dict(workload=name, n_circles=2000, container="unit square",
+                           iterations_per_step=args.iters, edges=prob.n_edges,
+                           slots=prob.n_slots, factors=prob.n_factors,
+                           rho=1.0, alpha=1.0, seed=1001),
+               roofline=roofline)
+
+    if args.calibrate_copy:
+        n = 512 * 1024 * 1024 // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = 4 * n
+
+    if not args.no_secondary:
+        secd = {}
+        p0 = W.workload("packing_tri10")
+        g0 = A.Graph.from_problem(p0, precision=A.FP32, device=0)
+        s0 = time_solve(g0, 2000, 5, 1, torch, stream)
+        secd["packing_tri10"] = dict(us_per_iteration=s0 / 2000 * 1e6,
+                                     edge_updates_per_s=p0.n_edges * 2000 / s0,
+                                     iterations=2000)
+        p2 = W.workload("svm_100k_d20")
+        g2 = A.Graph.from_problem(p2, precision=A.FP32, device=0)
+        s2 = time_solve(g2, 500, 5, 1, torch, stream)
+        g2.set_state(p2.z0)
+        x2, z2 = g2.run_profiled(500, stream)
+        inf2 = g2.info()
+        secd["svm_100k_d20"] = dict(edge_updates_per_s=p2.n_edges * 500 / s2,
+                                    ms_per_solve=s2 * 1e3, iterations=500,
+                                    xpass_avg_us=x2 * 1e3 / 500,
+                                    xpass_GBs=inf2["algo_bytes_per_iter"] / (x2 * 1e-3 / 500) / 1e9)
+        out["secondary"] = secd
+
+    if not args.no_cpu:
+        cb_iters = args.cpu_iters
+        v, dt = cpu_baseline(prob, cb_iters)
+        out["cpu_baseline"] = dict(value=v, unit="edge-updates/s", cores=1, kind="oracle",
+                                   sample=f"{name}: {cb_iters} iterations of the full graph "
+                                          f"({dt:.1f} s, serial FP64)")
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,174 @@
+/*
+ * admm.h - C ABI of the MI355X (gfx950) factor-graph ADMM library.
+ *
+ * The library runs the message-passing ADMM of Algorithm 2 (paper Sec. II,
+ * "ADMM on a factor-graph"): per iteration
+ *     x_(a,.) = Prox_{f_a,rho}(n_(a,.))        for every factor a   (x-update)
+ *     m_e     = x_e + u_e                     for every edge e     (m-update)
+ *     z_b     = sum_{a in db} rho m_(a,b) / sum_{a in db} rho      (z-update)
+ *     u_e     = u_e + alpha (x_e - z_b)                             (u-update)
+ *     n_e     = z_b - u_e                                           (n-update)
+ * where Prox_{h,rho}(r) = argmin_s h(s) + rho/2 |s - r|^2 (eq. (3)).
+ *
+ * Conventions for every function:
+ *  - Every entry point returns an admm_status; nothing throws across the
+ *    ABI.  On failure admm_last_error() returns a message for the calling
+ *    thread (valid until that thread's next call).
+ *  - Host arrays passed in are read during the call only; the caller keeps
+ *    ownership.  Device memory the library allocates is owned by the handle
+ *    and released by the matching destroy call.  Pointers documented as
+ *    "device" must point to memory of the handle's device.
+ *  - "stream" is a hipStream_t passed as void*; NULL means the null stream.
+ *    Functions that return host results synchronise that stream.
+ *  - A handle must not be used by two threads at the same time.
+ *  - Edge slots: an edge (a,b) carries dim(b) scalar slots.  "User slot
+ *    order" is the order in which edges were created: factors in the order
+ *    of admm_graph_add_factors calls and rows of var_ids, each factor's
+ *    edges in var_ids order, each edge's components in order (the layout
+ *    of the paper's edge arrays, Sec. III).
+ *  - z uses "variable order": variable 0's components, then variable 1's...
+ */
+#ifndef ADMM_H
+#define ADMM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  ADMM_OK = 0,
+  ADMM_E_ARG = 1,          /* invalid argument (ids, dims, sizes, nulls) */
+  ADMM_E_STATE = 2,        /* call out of order (e.g. run before finalize) */
+  ADMM_E_NUMERIC = 3,      /* parameter makes a prox ill-posed (rho <= gamma) */
+  ADMM_E_HIP = 4,          /* a HIP runtime call failed */
+  ADMM_E_OOM = 5,          /* device allocation failed */
+  ADMM_E_NO_DEVICE = 6,    /* no usable GPU (validation still ran) */
+  ADMM_E_UNSUPPORTED = 7   /* valid request outside this build's limits */
+} admm_status;
+
+/* Factor kinds (the proximal operators of the paper's appendix).
+ *  kind        edges (dims)              params (per factor, param_len)
+ *  NONOVERLAP  c1(2) r1(1) c2(2) r2(1)   none (0)             App. A, |c1-c2| >= r1+r2
+ *  WALL        c(2) r(1)                 Qx Qy Vx Vy (4)       App. A, Q^T(c-V) >= r
+ *  RADIUS      r(1)                      gamma (1)             App. A, -gamma/2 r^2, r >= 0
+ *  QUAD        any                       q_k per slot (slots)  App. B, 1/2 sum q_k x_k^2
+ *  BOX         any                       lo hi (2)             lo <= x_k <= hi
+ *  HINGE       w_1..w_d(1 each) b(1)     a_1..a_d y C (d+2)    App. C, C max(0, 1-y(w.a+b))
+ *  L2          any                       lambda (1)            App. C, lambda/2 |w|^2
+ *  LINDYN      x(n) u(m) x'(n)           A (n*n) B (n*m)       App. B, x' = A x + B u
+ *  LINDYN0     u(m) x'(n)                A B x0 (n*n+n*m+n)    App. B, x' = A x0 + B u
+ * Matrices are row-major.  The prox of NONOVERLAP moves the radii by -D/4
+ * (the sign that makes the output feasible) and uses the direction (1,0)
+ * when the two centres coincide; RADIUS requires rho > gamma. */
+typedef enum {
+  ADMM_F_NONOVERLAP = 1,
+  ADMM_F_WALL = 2,
+  ADMM_F_RADIUS = 3,
+  ADMM_F_QUAD = 4,
+  ADMM_F_BOX = 5,
+  ADMM_F_HINGE = 6,
+  ADMM_F_L2 = 7,
+  ADMM_F_LINDYN = 8,
+  ADMM_F_LINDYN0 = 9
+} admm_factor_kind;
+
+typedef enum { ADMM_FP32 = 0, ADMM_FP64 = 1 } admm_precision;
+
+typedef struct admm_graph admm_graph;
+
+/* Sizes and layout of a finalized graph (all counts, no pointers). */
+typedef struct {
+  int64_t n_vars, n_scalars, n_factors, n_edges, n_slots;
+  int64_t n_buckets;           /* factor buckets after type bucketing */
+  int64_t n_pair_tiles;        /* tiles of the dense pairwise layout (0 if none) */
+  int64_t n_contributions;     /* entries summed by the z-update */
+  int64_t state_bytes;         /* per-edge state resident in device memory */
+  int64_t algo_bytes_per_iter; /* algorithmic HBM bytes of one iteration */
+  int64_t layout_bytes_per_iter; /* index/partial bytes of one iteration */
+  int32_t precision;           /* admm_precision */
+  int32_t alpha_is_one;        /* 1: m-only state (alpha == 1) */
+} admm_graph_info;
+
+/* Message for the last failing call on this thread ("" if none). */
+const char* admm_last_error(void);
+/* ABI version of this header (incremented on incompatible change). */
+int32_t admm_abi_version(void);
+
+/* Create an empty graph with n_vars variable nodes; var_dim[n_vars] gives
+ * each variable's dimension (>= 1).  precision: admm_precision of all
+ * device arithmetic.  Paper Sec. III: the graph the user extends node by
+ * node ("addNode"). */
+admm_status admm_graph_create(int32_t n_vars, const int32_t* var_dim,
+                              int32_t precision, admm_graph** out);
+
+/* Append n_factors factors of one kind, each connected to `arity` variables:
+ * var_ids[n_factors*arity] (row-major, edge order per factor).  params:
+ * [n_factors*param_len] doubles, or [param_len] shared by all when
+ * shared_params != 0 (NULL allowed when param_len == 0).  Dimensions and
+ * param_len are checked against the kind's signature (table above);
+ * violations return ADMM_E_ARG.  Only before finalize. */
+admm_status admm_graph_add_factors(admm_graph* g, int32_t kind,
+                                   int32_t n_factors, int32_t arity,
+                                   const int32_t* var_ids,
+                                   const double* params, int32_t param_len,
+                                   int32_t shared_params);
+
+/* rho (> 0) and alpha (> 0) of every edge (Alg. 2; one value for all
+ * edges).  Defaults 1 and 1.  Only before finalize. */
+admm_status admm_graph_set_rho(admm_graph* g, double rho);
+admm_status admm_graph_set_alpha(admm_graph* g, double alpha);
+
+/* Validate, bucket factors by kind, build the device layout (edge-major
+ * structure-of-arrays per bucket, dense pair tiles for complete pairwise
+ * non-overlap buckets, per-variable contribution lists) and upload it to
+ * `device`.  Sets z to 0 and u to 0.  Returns ADMM_E_NO_DEVICE (after full
+ * validation) when no GPU is present, ADMM_E_NUMERIC when rho <= gamma for a
+ * RADIUS factor. */
+admm_status admm_graph_finalize(admm_graph* g, int32_t device);
+
+admm_status admm_graph_info_get(const admm_graph* g, admm_graph_info* info);
+
+/* Set the iteration state from host arrays: z[n_scalars] in variable order
+ * and u[n_slots] in user slot order (NULL: u = 0).  The next x-update uses
+ * n = z - u. */
+admm_status admm_set_state(admm_graph* g, const double* z, const double* u,
+                           void* stream);
+
+/* Run `iters` >= 0 iterations of Algorithm 2 on the device, enqueued on
+ * `stream` without host round-trips.  The last iteration also records
+ * what admm_get_residuals and admm_get_x return. */
+admm_status admm_run(admm_graph* g, int32_t iters, void* stream);
+
+/* admm_run with a HIP event pair around every kernel: same results, and
+ * the summed device time of the x-passes and of the z-passes in
+ * milliseconds.  Synchronises the stream.  For measurement only: the
+ * events add a small gap between kernels. */
+admm_status admm_run_profiled(admm_graph* g, int32_t iters, void* stream,
+                              double* xpass_ms, double* zpass_ms);
+
+/* Copy results to host arrays (double).  z: [n_scalars] variable order;
+ * u and x: [n_slots] user slot order (x of the last iteration run). */
+admm_status admm_get_z(admm_graph* g, double* z, void* stream);
+admm_status admm_get_u(admm_graph* g, double* u, void* stream);
+admm_status admm_get_x(admm_graph* g, double* x, void* stream);
+
+/* Residuals of the last iteration run: r = max_e |x_e - z_b| and
+ * s = rho max_b |z_b - z_b(previous iteration)| (the paper leaves the
+ * stopping criterion open; these are the infinity-norm measures used
+ * throughout this library). */
+admm_status admm_get_residuals(admm_graph* g, double* r_primal,
+                               double* r_dual, void* stream);
+
+/* Device address of z (working precision, variable order) for callers that
+ * read it in place; valid until the next run or destroy. */
+admm_status admm_z_device_ptr(admm_graph* g, void** z_dev);
+
+admm_status admm_graph_destroy(admm_graph* g);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ADMM_H */

@@ -1,0 +1,1089 @@
+// Factor-graph ADMM engine: host-side graph compiler and the C ABI of
+// include/admm.h for graphs.
+//
+// The compiler turns the user's factor lists (paper Sec. III: nodes added
+// one call at a time, edges stored in creation order) into a device layout
+// built for gfx950 instead of the paper's one-array-per-variable-kind
+// layout:
+//  - factors are bucketed by proximal-operator kind, so every workgroup of
+//    the fused x-pass runs a single operator;
+//  - per-edge state is structure-of-arrays, [slot][factor], so a wavefront
+//    streams each slot with unit stride;
+//  - complete pairwise non-overlap buckets (every unordered pair of disks
+//    once, as in circle packing) are stored as dense 64x64 pair tiles with
+//    implicit indices, and each tile emits row/column partial sums;
+//  - hinge buckets whose factors share one variable list (the SVM) emit one
+//    partial per variable per workgroup;
+//  - everything else keeps explicit per-edge variable offsets, and the
+//    z-update sums its m slots directly.
+// Each scalar of z gets a list of contributions (partials or m slots) in a
+// fixed order, which the z-pass sums deterministically.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <numeric>
+#include <vector>
+
+#include "graph_kernels.h"
+
+using namespace admmg;
+
+namespace {
+
+struct Group {
+  int32_t kind, n, arity, plen;
+  bool shared;
+  std::vector<int32_t> vids;   // [n * arity]
+  std::vector<double> params;  // [n * plen] or [plen]
+  const double* prm(int64_t f) const {
+    return plen == 0 ? nullptr : params.data() + (shared ? 0 : f * (int64_t)plen);
+  }
+};
+
+// Host layout of a finalized graph (precision independent).
+struct Plan {
+  std::vector<BucketDesc> bt;
+  std::vector<int32_t> idx;
+  std::vector<double> par;
+  int64_t n_part = 0, n_m = 0;  // partial and m-region element counts
+  std::vector<uint32_t> csr;    // contribution pool positions
+  std::vector<int32_t> var_w, var_l;
+  std::vector<int64_t> rng_w, rng_l;
+  std::vector<double> deg_w, deg_l;
+  std::vector<int64_t> upos;    // user slot -> pool position of m
+  std::vector<int32_t> uz;      // user slot -> z index
+  int64_t xblocks = 0;
+  int64_t algo_bytes = 0, layout_bytes = 0;  // per iteration, in T units x sizeof later
+  int64_t algo_elems = 0, layout_idx_bytes = 0, layout_elems = 0;
+  int64_t n_pair_tiles = 0;
+};
+
+struct EngineBase {
+  virtual ~EngineBase() {}
+  virtual admm_status upload(const Plan& p, const std::vector<double>& z0, double rho,
+                             double alpha) = 0;
+  virtual admm_status set_state(const double* z, const double* u, hipStream_t s) = 0;
+  virtual admm_status run(int32_t iters, hipStream_t s) = 0;
+  virtual admm_status run_profiled(int32_t iters, hipStream_t s, double* x_ms, double* z_ms) = 0;
+  virtual admm_status get_z(double* z, hipStream_t s) = 0;
+  virtual admm_status get_slots(double* out, int which, hipStream_t s) = 0;
+  virtual admm_status residuals(double* r, double* s, hipStream_t st) = 0;
+  virtual void* z_ptr() = 0;
+};
+
+}  // namespace
+
+struct admm_graph {
+  int32_t precision = ADMM_FP32;
+  std::vector<int32_t> dim;
+  std::vector<int64_t> zoff;
+  int64_t nz = 0;
+  std::vector<Group> groups;
+  double rho = 1.0, alpha = 1.0;
+  int64_t n_factors = 0, n_edges = 0, n_slots = 0;
+  int state = 0;  // 0 building, 1 validated (no device), 2 ready
+  int device = -1;
+  Plan plan;
+  admm_graph_info info{};
+  std::unique_ptr<EngineBase> eng;
+};
+
+namespace {
+
+inline int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
+
+int32_t kind_dim_ok(const admm_graph& g, const Group& gr, std::string& why, int32_t& nn,
+                    int32_t& mm) {
+  const int A = gr.arity;
+  auto D = [&](int64_t f, int e) { return g.dim[gr.vids[f * A + e]]; };
+  nn = mm = 0;
+  switch (gr.kind) {
+    case KD_NONOVERLAP:
+      if (A != 4 || gr.plen != 0) { why = "NONOVERLAP needs arity 4 and no params"; return 0; }
+      for (int64_t f = 0; f < gr.n; ++f)
+        if (D(f, 0) != 2 || D(f, 1) != 1 || D(f, 2) != 2 || D(f, 3) != 1) {
+          why = "NONOVERLAP edges must have dims (2,1,2,1)"; return 0;
+        }
+      return 1;
+    case KD_WALL:
+      if (A != 2 || gr.plen != 4) { why = "WALL needs arity 2 and 4 params"; return 0; }
+      for (int64_t f = 0; f < gr.n; ++f)
+        if (D(f, 0) != 2 || D(f, 1) != 1) { why = "WALL edges must have dims (2,1)"; return 0; }
+      return 1;
+    case KD_RADIUS:
+      if (A != 1 || gr.plen != 1) { why = "RADIUS needs arity 1 and 1 param"; return 0; }
+      for (int64_t f = 0; f < gr.n; ++f)
+        if (D(f, 0) != 1) { why = "RADIUS edge must have dim 1"; return 0; }
+      return 1;
+    case KD_QUAD:
+      for (int64_t f = 0; f < gr.n; ++f) {
+        int k = 0;
+        for (int e = 0; e < A; ++e) k += D(f, e);
+        if (k != gr.plen) { why = "QUAD needs one weight per scalar slot"; return 0; }
+      }
+      return 1;
+    case KD_BOX:
+      if (gr.plen != 2) { why = "BOX needs 2 params (lo, hi)"; return 0; }
+      for (int64_t f = 0; f < gr.n; ++f)
+        if (gr.prm(f)[0] > gr.prm(f)[1]) { why = "BOX needs lo <= hi"; return 0; }
+      return 1;
+    case KD_HINGE:
+      if (A < 2 || gr.plen != A + 1) { why = "HINGE needs arity d+1 >= 2 and d+2 params"; return 0; }
+      for (int64_t f = 0; f < gr.n; ++f) {
+        for (int e = 0; e < A; ++e)
+          if (D(f, e) != 1) { why = "HINGE edges must be scalar"; return 0; }
+        if (gr.prm(f)[A] < 0) { why = "HINGE needs C >= 0"; return 0; }
+      }
+      return 1;
+    case KD_L2:
+      if (gr.plen != 1) { why = "L2 needs 1 param"; return 0; }
+      return 1;
+    case KD_LINDYN:
+    case KD_LINDYN0: {
+      const bool first = gr.kind == KD_LINDYN0;
+      if (A != (first ? 2 : 3)) { why = "LINDYN needs arity 3, LINDYN0 arity 2"; return 0; }
+      for (int64_t f = 0; f < gr.n; ++f) {
+        int n = first ? D(f, 1) : D(f, 0), m = first ? D(f, 0) : D(f, 1);
+        if (!first && D(f, 2) != n) { why = "LINDYN edges must have dims (n,m,n)"; return 0; }
+        if (f == 0) { nn = n; mm = m; }
+        if (n != nn || m != mm) { why = "LINDYN dims must agree within one call"; return 0; }
+      }
+      if (gr.plen != nn * nn + nn * mm + (first ? nn : 0)) { why = "LINDYN param_len mismatch"; return 0; }
+      return 1;
+    }
+    default:
+      why = "unknown factor kind";
+      return 0;
+  }
+}
+
+// Inverse of a small symmetric positive definite matrix (Gauss-Jordan).
+std::vector<double> spd_inverse(std::vector<double> a, int n) {
+  std::vector<double> inv(n * n, 0.0);
+  for (int i = 0; i < n; ++i) inv[i * n + i] = 1.0;
+  for (int c = 0; c < n; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < n; ++r)
+      if (std::fabs(a[r * n + c]) > std::fabs(a[piv * n + c])) piv = r;
+    for (int j = 0; j < n; ++j) {
+      std::swap(a[c * n + j], a[piv * n + j]);
+      std::swap(inv[c * n + j], inv[piv * n + j]);
+    }
+    const double d = a[c * n + c];
+    for (int j = 0; j < n; ++j) { a[c * n + j] /= d; inv[c * n + j] /= d; }
+    for (int r = 0; r < n; ++r) {
+      if (r == c) continue;
+      const double f = a[r * n + c];
+      if (f == 0.0) continue;
+      for (int j = 0; j < n; ++j) { a[r * n + j] -= f * a[c * n + j]; inv[r * n + j] -= f * inv[c * n + j]; }
+    }
+  }
+  return inv;
+}
+
+// True when a NONOVERLAP bucket lists every unordered pair of "entities"
+// (a centre variable and its radius variable) exactly once, each factor
+// naming the entity with the smaller centre id first.  Fills the entities'
+// z offsets and the entity pair of every factor.
+bool detect_complete_pairs(const admm_graph& g, const Group& gr, std::vector<int32_t>& ent_zc,
+                           std::vector<int32_t>& ent_zr, std::vector<int32_t>& fe1,
+                           std::vector<int32_t>& fe2) {
+  const int32_t nv = (int32_t)g.dim.size();
+  std::vector<int32_t> c2r(nv, -1), r2c(nv, -1);
+  for (int64_t f = 0; f < gr.n; ++f)
+    for (int h = 0; h < 2; ++h) {
+      const int32_t c = gr.vids[f * 4 + 2 * h], r = gr.vids[f * 4 + 2 * h + 1];
+      if (c2r[c] < 0) c2r[c] = r; else if (c2r[c] != r) return false;
+      if (r2c[r] < 0) r2c[r] = c; else if (r2c[r] != c) return false;
+    }
+  // entities in increasing order of their centre variable id
+  std::vector<int32_t> eid(nv, -1);
+  ent_zc.clear();
+  ent_zr.clear();
+  for (int32_t c = 0; c < nv; ++c) {
+    if (c2r[c] < 0) continue;
+    eid[c] = (int32_t)ent_zc.size();
+    ent_zc.push_back((int32_t)g.zoff[c]);
+    ent_zr.push_back((int32_t)g.zoff[c2r[c]]);
+  }
+  const int64_t E = (int64_t)ent_zc.size();
+  if (E < 2 || gr.n != E * (E - 1) / 2) return false;
+  fe1.resize(gr.n);
+  fe2.resize(gr.n);
+  std::vector<uint8_t> seen((size_t)E * E, 0);
+  for (int64_t f = 0; f < gr.n; ++f) {
+    const int32_t a = eid[gr.vids[f * 4]], b = eid[gr.vids[f * 4 + 2]];
+    if (a >= b) return false;
+    if (seen[(size_t)a * E + b]) return false;
+    seen[(size_t)a * E + b] = 1;
+    fe1[f] = a;
+    fe2[f] = b;
+  }
+  return true;
+}
+
+bool hinge_uniform(const Group& gr) {
+  for (int64_t f = 1; f < gr.n; ++f)
+    for (int e = 0; e < gr.arity; ++e)
+      if (gr.vids[f * gr.arity + e] != gr.vids[e]) return false;
+  return gr.n >= 1;
+}
+
+// Build the device layout.  Validation errors return non-OK.
+admm_status build_plan(admm_graph& g, Plan& P) {
+  P = Plan();
+  struct Emit { int64_t z; int64_t pos; };  // pos: m-region or partial index
+  std::vector<Emit> em_part, em_m;          // contributions, in emission order
+  std::vector<int64_t> deg(g.nz, 0);
+  P.upos.assign(g.n_slots, 0);
+  P.uz.assign(g.n_slots, 0);
+  int64_t us = 0;      // running user slot
+  int64_t blocks = 0;
+  for (const Group& gr : g.groups) {
+    std::string why;
+    int32_t nn = 0, mm = 0;
+    if (!kind_dim_ok(g, gr, why, nn, mm)) return admmi::set_err(ADMM_E_ARG, "%s", why.c_str());
+    if (gr.kind == KD_RADIUS)
+      for (int64_t f = 0; f < gr.n; ++f)
+        if (!(g.rho > gr.prm(f)[0]))
+          return admmi::set_err(ADMM_E_NUMERIC, "RADIUS factor needs rho > gamma (rho=%g, gamma=%g)",
+                                g.rho, gr.prm(f)[0]);
+    if (gr.n == 0) continue;
+    BucketDesc b{};
+    b.kind = gr.kind;
+    b.arity = gr.arity;
+    b.idx_off = (int64_t)P.idx.size();
+    b.par_off = (int64_t)P.par.size();
+    b.m_off = P.n_m;
+    // slots per factor (constant within a group for every kind but QUAD/BOX/L2)
+    auto fslots = [&](int64_t f) {
+      int k = 0;
+      for (int e = 0; e < gr.arity; ++e) k += g.dim[gr.vids[f * gr.arity + e]];
+      return k;
+    };
+    // user-slot walk helper: for factor f, edge e, comp c -> z index
+    auto zof = [&](int64_t f, int e) { return g.zoff[gr.vids[f * gr.arity + e]]; };
+
+    std::vector<int32_t> ezc, ezr, fe1, fe2;
+    const bool separable = gr.kind == KD_RADIUS || gr.kind == KD_QUAD || gr.kind == KD_BOX ||
+                           gr.kind == KD_L2;
+    if (gr.kind == KD_NONOVERLAP && detect_complete_pairs(g, gr, ezc, ezr, fe1, fe2)) {
+      // ---------------- dense pair tiles ----------------
+      b.mode = BM_PAIR;
+      b.E = (int32_t)ezc.size();
+      b.NB = (b.E + PB - 1) / PB;
+      b.nslot = 6;
+      std::vector<int32_t> tI, tJ;
+      std::vector<int64_t> tid((size_t)b.NB * b.NB, -1);
+      for (int I = 0; I < b.NB; ++I)
+        for (int J = I; J < b.NB; ++J) {
+          tid[(size_t)I * b.NB + J] = (int64_t)tI.size();
+          tI.push_back(I);
+          tJ.push_back(J);
+        }
+      b.n = (int64_t)tI.size();
+      b.nfp = b.n;
+      P.n_pair_tiles += b.n;
+      for (int64_t t = 0; t < b.n; ++t) { P.idx.push_back(tI[t]); P.idx.push_back(tJ[t]); }
+      for (int e = 0; e < b.E; ++e) { P.idx.push_back(ezc[e]); P.idx.push_back(ezr[e]); }
+      const int64_t TS = 6 * PB * PB;
+      P.n_m += b.n * TS;
+      b.part_off = P.n_part;
+      P.n_part += b.n * 6 * PB;
+      b.blk0 = (int32_t)blocks;
+      blocks += b.n;
+      b.blk1 = (int32_t)blocks;
+      // contributions: per tile, rows then columns with at least one pair
+      for (int64_t t = 0; t < b.n; ++t) {
+        const int I = tI[t], J = tJ[t];
+        const int64_t pb = b.part_off + t * 6 * PB;
+        for (int li = 0; li < PB; ++li) {
+          const int ei = I * PB + li;
+          if (ei >= b.E) break;
+          int cnt = 0;
+          for (int lj = 0; lj < PB; ++lj) {
+            const int ej = J * PB + lj;
+            if (ej < b.E && (I != J || li < lj)) ++cnt;
+          }
+          if (!cnt) continue;
+          em_part.push_back({ezc[ei], pb + li * 3});
+          em_part.push_back({ezc[ei] + 1, pb + li * 3 + 1});
+          em_part.push_back({ezr[ei], pb + li * 3 + 2});
+        }
+        for (int lj = 0; lj < PB; ++lj) {
+          const int ej = J * PB + lj;
+          if (ej >= b.E) break;
+          const bool any = (I != J) ? true : (lj > 0);
+          if (!any) continue;
+          em_part.push_back({ezc[ej], pb + 3 * PB + lj * 3});
+          em_part.push_back({ezc[ej] + 1, pb + 3 * PB + lj * 3 + 1});
+          em_part.push_back({ezr[ej], pb + 3 * PB + lj * 3 + 2});
+        }
+      }
+      for (int64_t f = 0; f < gr.n; ++f) {
+        const int e1 = fe1[f], e2 = fe2[f];
+        const int I = e1 / PB, li = e1 % PB, J = e2 / PB, lj = e2 % PB;
+        const int64_t t = tid[(size_t)I * b.NB + J];
+        const int64_t base = b.m_off + t * TS + li * PB + lj;
+        const int64_t zs[6] = {ezc[e1], ezc[e1] + 1, ezr[e1], ezc[e2], ezc[e2] + 1, ezr[e2]};
+        for (int s = 0; s < 6; ++s) {
+          P.upos[us] = base + (int64_t)s * PB * PB;
+          P.uz[us] = (int32_t)zs[s];
+          deg[zs[s]]++;
+          ++us;
+        }
+      }
+      P.algo_elems += 2 * (int64_t)gr.n * 6;
+      P.layout_elems += b.n * 6 * PB;  // partial writes
+    } else if (gr.kind == KD_HINGE && gr.arity - 1 <= 64 && hinge_uniform(gr)) {
+      // ---------------- hinge, shared variable list ----------------
+      b.mode = BM_UNIF_HINGE;
+      b.d = gr.arity - 1;
+      b.dmax = b.d <= 32 ? 32 : 64;
+      b.n = gr.n;
+      b.nfp = round_up(gr.n, 64);
+      b.nslot = gr.arity;
+      for (int e = 0; e < gr.arity; ++e) P.idx.push_back((int32_t)zof(0, e));
+      const int d = b.d;
+      P.par.resize(P.par.size() + (size_t)(d + 3) * b.nfp, 0.0);
+      double* par = P.par.data() + b.par_off;
+      for (int64_t f = 0; f < gr.n; ++f) {
+        const double* p = gr.prm(f);
+        const double y = p[d], C = p[d + 1];
+        double aa = 0.0;
+        for (int k = 0; k < d; ++k) { par[k * b.nfp + f] = y * p[k]; aa += p[k] * p[k]; }
+        par[d * b.nfp + f] = y;
+        par[(d + 1) * b.nfp + f] = C;
+        par[(d + 2) * b.nfp + f] = g.rho / (aa + 1.0);
+      }
+      P.n_m += (int64_t)gr.arity * b.nfp;
+      const int64_t tiles = (gr.n + NT - 1) / NT;
+      b.part_off = P.n_part;
+      P.n_part += tiles * gr.arity;
+      b.blk0 = (int32_t)blocks;
+      blocks += tiles;
+      b.blk1 = (int32_t)blocks;
+      for (int64_t t = 0; t < tiles; ++t)
+        for (int e = 0; e < gr.arity; ++e) em_part.push_back({zof(0, e), b.part_off + t * gr.arity + e});
+      for (int64_t f = 0; f < gr.n; ++f)
+        for (int e = 0; e < gr.arity; ++e) {
+          P.upos[us] = b.m_off + (int64_t)e * b.nfp + f;
+          P.uz[us] = (int32_t)zof(f, e);
+          deg[zof(f, e)]++;
+          ++us;
+        }
+      P.algo_elems += (int64_t)gr.n * (2 * gr.arity + d + 3);
+      P.layout_elems += tiles * gr.arity;
+    } else if (separable) {
+      // ---------------- separable operators: one thread per slot ----------------
+      b.mode = BM_GEN_SLOT;
+      int64_t ns = 0;
+      for (int64_t f = 0; f < gr.n; ++f) ns += fslots(f);
+      b.n = ns;
+      b.nfp = round_up(ns, 64);
+      b.nslot = 1;
+      const int64_t i0 = (int64_t)P.idx.size();
+      P.idx.resize(i0 + b.nfp, 0);
+      P.par.resize(P.par.size() + 2 * (size_t)b.nfp, 0.0);
+      double* par = P.par.data() + b.par_off;
+      int64_t s = 0;
+      for (int64_t f = 0; f < gr.n; ++f) {
+        const double* p = gr.prm(f);
+        int comp = 0;
+        for (int e = 0; e < gr.arity; ++e) {
+          const int dm = g.dim[gr.vids[f * gr.arity + e]];
+          for (int c = 0; c < dm; ++c, ++comp, ++s) {
+            const int64_t zi = zof(f, e) + c;
+            P.idx[i0 + s] = (int32_t)zi;
+            double p0 = 0.0, p1 = 0.0;
+            switch (gr.kind) {
+              case KD_RADIUS: p0 = g.rho / (g.rho - p[0]); break;
+              case KD_QUAD: p0 = g.rho / (g.rho + p[comp]); break;
+              case KD_L2: p0 = g.rho / (g.rho + p[0]); break;
+              case KD_BOX: p0 = p[0]; p1 = p[1]; break;
+            }
+            par[s] = p0;
+            par[b.nfp + s] = p1;
+            P.upos[us] = b.m_off + s;
+            P.uz[us] = (int32_t)zi;
+            deg[zi]++;
+            ++us;
+            em_m.push_back({zi, b.m_off + s});
+          }
+        }
+      }
+      P.n_m += b.nfp;
+      b.blk0 = (int32_t)blocks;
+      blocks += (ns + NT - 1) / NT;
+      b.blk1 = (int32_t)blocks;
+      P.algo_elems += ns * (2 + (gr.kind == KD_BOX ? 2 : 1));
+      P.layout_idx_bytes += ns * 4;
+    } else {
+      // ---------------- general: one thread per factor ----------------
+      b.mode = BM_GEN_FACTOR;
+      b.n = gr.n;
+      b.nfp = round_up(gr.n, 64);
+      b.nslot = fslots(0);
+      if (gr.kind == KD_HINGE) {
+        b.d = gr.arity - 1;
+        if (b.d > 64) return admmi::set_err(ADMM_E_UNSUPPORTED, "HINGE with d > 64 is not supported");
+        b.dmax = b.d <= 32 ? 32 : 64;
+      }
+      if (gr.kind == KD_LINDYN || gr.kind == KD_LINDYN0) {
+        b.nn = nn;
+        b.mm = mm;
+        if (nn > MAXN || mm > MAXM)
+          return admmi::set_err(ADMM_E_UNSUPPORTED, "LINDYN supports n <= %d, m <= %d", MAXN, MAXM);
+      }
+      const int64_t i0 = (int64_t)P.idx.size();
+      const bool lind = gr.kind == KD_LINDYN || gr.kind == KD_LINDYN0;
+      P.idx.resize(i0 + (int64_t)(gr.arity + (lind ? 1 : 0)) * b.nfp, 0);
+      for (int64_t f = 0; f < gr.n; ++f)
+        for (int e = 0; e < gr.arity; ++e) P.idx[i0 + e * b.nfp + f] = (int32_t)zof(f, e);
+      if (gr.kind == KD_WALL) {
+        P.par.resize(P.par.size() + 4 * (size_t)b.nfp, 0.0);
+        double* par = P.par.data() + b.par_off;
+        for (int64_t f = 0; f < gr.n; ++f) {
+          const double* p = gr.prm(f);
+          par[f] = p[0];
+          par[b.nfp + f] = p[1];
+          par[2 * b.nfp + f] = p[0] * p[2] + p[1] * p[3];
+          par[3 * b.nfp + f] = 1.0 / (p[0] * p[0] + p[1] * p[1] + 1.0);
+        }
+        P.algo_elems += gr.n * 4;
+      } else if (gr.kind == KD_HINGE) {
+        const int d = b.d;
+        P.par.resize(P.par.size() + (size_t)(d + 3) * b.nfp, 0.0);
+        double* par = P.par.data() + b.par_off;
+        for (int64_t f = 0; f < gr.n; ++f) {
+          const double* p = gr.prm(f);
+          double aa = 0.0;
+          for (int k = 0; k < d; ++k) { par[k * b.nfp + f] = p[d] * p[k]; aa += p[k] * p[k]; }
+          par[d * b.nfp + f] = p[d];
+          par[(d + 1) * b.nfp + f] = p[d + 1];
+          par[(d + 2) * b.nfp + f] = g.rho / (aa + 1.0);
+        }
+        P.algo_elems += gr.n * (d + 3);
+      } else if (lind) {
+        // parameter blocks: one per factor, or one for the group when shared
+        const int n = nn, m = mm;
+        const bool first = gr.kind == KD_LINDYN0;
+        const int k = first ? m : n + m;
+        const int64_t nblk = gr.shared ? 1 : gr.n;
+        const int64_t bl = (int64_t)n * k + (int64_t)n * n + (first ? n : 0);
+        for (int64_t q = 0; q < nblk; ++q) {
+          const double* p = gr.prm(q);
+          const double* A = p;
+          const double* B = p + n * n;
+          std::vector<double> Mx((size_t)n * k);
+          for (int r = 0; r < n; ++r) {
+            if (first) {
+              for (int j = 0; j < m; ++j) Mx[r * k + j] = B[r * m + j];
+            } else {
+              for (int j = 0; j < n; ++j) Mx[r * k + j] = A[r * n + j];
+              for (int j = 0; j < m; ++j) Mx[r * k + n + j] = B[r * m + j];
+            }
+          }
+          std::vector<double> G((size_t)n * n, 0.0);
+          for (int r = 0; r < n; ++r)
+            for (int c = 0; c < n; ++c) {
+              double s = (r == c) ? 1.0 : 0.0;
+              for (int j = 0; j < k; ++j) s += Mx[r * k + j] * Mx[c * k + j];
+              G[r * n + c] = s;
+            }
+          std::vector<double> S = spd_inverse(G, n);
+          const int64_t off = (int64_t)P.par.size() - b.par_off;
+          P.par.insert(P.par.end(), Mx.begin(), Mx.end());
+          P.par.insert(P.par.end(), S.begin(), S.end());
+          if (first) {
+            const double* x0 = p + n * n + n * m;
+            for (int r = 0; r < n; ++r) {
+              double s = 0.0;
+              for (int j = 0; j < n; ++j) s += A[r * n + j] * x0[j];
+              P.par.push_back(s);
+            }
+          }
+          if (gr.shared) {
+            for (int64_t f = 0; f < gr.n; ++f) P.idx[i0 + gr.arity * b.nfp + f] = (int32_t)off;
+          } else {
+            P.idx[i0 + gr.arity * b.nfp + q] = (int32_t)off;
+          }
+          (void)bl;
+        }
+      }
+      P.n_m += (int64_t)b.nslot * b.nfp;
+      for (int64_t f = 0; f < gr.n; ++f) {
+        int s = 0;
+        for (int e = 0; e < gr.arity; ++e) {
+          const int dm = g.dim[gr.vids[f * gr.arity + e]];
+          for (int c = 0; c < dm; ++c, ++s) {
+            const int64_t zi = zof(f, e) + c;
+            const int64_t pos = b.m_off + (int64_t)s * b.nfp + f;
+            P.upos[us] = pos;
+            P.uz[us] = (int32_t)zi;
+            deg[zi]++;
+            ++us;
+            em_m.push_back({zi, pos});
+          }
+        }
+      }
+      b.blk0 = (int32_t)blocks;
+      blocks += (gr.n + NT - 1) / NT;
+      b.blk1 = (int32_t)blocks;
+      P.algo_elems += 2 * (int64_t)gr.n * b.nslot;
+      P.layout_idx_bytes += (int64_t)gr.n * gr.arity * 4;
+    }
+    P.bt.push_back(b);
+  }
+  if (us != g.n_slots) return admmi::set_err(ADMM_E_ARG, "internal: slot count mismatch");
+  if (blocks > 0x7fffffff) return admmi::set_err(ADMM_E_UNSUPPORTED, "graph too large for one launch");
+  P.xblocks = blocks;
+  // pool = [partials | m regions | x regions]: shift m offsets past partials
+  for (BucketDesc& b : P.bt) {
+    b.m_off += P.n_part;
+    b.x_off = b.m_off + P.n_m;
+  }
+  for (auto& v : P.upos) v += P.n_part;
+  for (auto& e : em_m) e.pos += P.n_part;
+  if (P.n_part + P.n_m > 0xffffffffLL)
+    return admmi::set_err(ADMM_E_UNSUPPORTED, "more than 2^32 state elements");
+  // contribution lists: counting sort by z index, emission order kept
+  std::vector<int64_t> cnt(g.nz + 1, 0);
+  for (auto& e : em_part) cnt[e.z + 1]++;
+  for (auto& e : em_m) cnt[e.z + 1]++;
+  for (int64_t i = 0; i < g.nz; ++i) cnt[i + 1] += cnt[i];
+  P.csr.assign(cnt[g.nz], 0);
+  std::vector<int64_t> fill(cnt.begin(), cnt.end() - 1);
+  for (auto& e : em_part) P.csr[fill[e.z]++] = (uint32_t)e.pos;
+  for (auto& e : em_m) P.csr[fill[e.z]++] = (uint32_t)e.pos;
+  for (int64_t zi = 0; zi < g.nz; ++zi) {
+    const int64_t len = cnt[zi + 1] - cnt[zi];
+    if (len > LANE_MAX) {
+      P.var_w.push_back((int32_t)zi);
+      P.rng_w.push_back(cnt[zi]);
+      P.rng_w.push_back(cnt[zi + 1]);
+      P.deg_w.push_back((double)deg[zi]);
+    } else {
+      P.var_l.push_back((int32_t)zi);
+      P.rng_l.push_back(cnt[zi]);
+      P.rng_l.push_back(cnt[zi + 1]);
+      P.deg_l.push_back((double)std::max<int64_t>(deg[zi], 1));
+    }
+  }
+  P.layout_elems += (int64_t)P.csr.size();
+  P.layout_idx_bytes += (int64_t)P.csr.size() * 4;
+  return ADMM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Device engine for one working precision.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct Engine : EngineBase {
+  int device = 0;
+  bool alpha1 = true;
+  T alpha = T(1), inv_rho = T(1);
+  int nb = 0;
+  int fs = FS_ALL;  // x-pass feature set
+  int64_t xblocks = 0, zblocks = 0, nb_w = 0, n_w = 0, n_l = 0, n_slots = 0, nz = 0, xdelta = 0;
+  T* pool = nullptr;
+  T* par = nullptr;
+  int32_t* idx = nullptr;
+  BucketDesc* bt = nullptr;
+  T* z[2] = {nullptr, nullptr};
+  int zc = 0;
+  uint32_t* csr = nullptr;
+  int32_t *var_w = nullptr, *var_l = nullptr;
+  int64_t *rng_w = nullptr, *rng_l = nullptr;
+  T *deg_w = nullptr, *deg_l = nullptr;
+  int64_t* upos = nullptr;
+  int32_t* uz = nullptr;
+  T *bmx = nullptr, *bmz = nullptr;
+  double* io = nullptr;
+  int64_t io_n = 0;
+  bool have_resid = false;
+  std::vector<void*> allocs;
+
+  ~Engine() override {
+    if (!allocs.empty()) {
+      hipSetDevice(device);
+      for (void* p : allocs) hipFree(p);
+    }
+  }
+
+  template <typename U>
+  admm_status alloc(U** p, int64_t n) {
+    *p = nullptr;
+    const size_t bytes = (size_t)std::max<int64_t>(n, 1) * sizeof(U);
+    ADMM_HIP(hipMalloc((void**)p, bytes));
+    allocs.push_back(*p);
+    return ADMM_OK;
+  }
+
+  template <typename U>
+  admm_status put(U** p, const std::vector<U>& v) {
+    admm_status s = alloc(p, (int64_t)v.size());
+    if (s) return s;
+    if (!v.empty()) ADMM_HIP(hipMemcpy(*p, v.data(), v.size() * sizeof(U), hipMemcpyHostToDevice));
+    return ADMM_OK;
+  }
+
+  admm_status put_conv(T** p, const std::vector<double>& v) {
+    std::vector<T> t(v.begin(), v.end());
+    return put(p, t);
+  }
+
+  admm_status upload(const Plan& P, const std::vector<double>& z0, double rho,
+                     double alpha_) override {
+    alpha1 = (alpha_ == 1.0);
+    alpha = (T)alpha_;
+    inv_rho = (T)(1.0 / rho);
+    nb = (int)P.bt.size();
+    xblocks = P.xblocks;
+    {
+      int need = 0;
+      for (const BucketDesc& b : P.bt) {
+        if (b.mode == BM_PAIR) need |= FT_PAIR;
+        else if (b.mode == BM_UNIF_HINGE && b.dmax <= 32) need |= FT_UHINGE;
+        else if (b.mode == BM_GEN_SLOT || b.kind == KD_NONOVERLAP || b.kind == KD_WALL) need |= FT_GEN;
+        else need |= FT_WIDE;
+      }
+      fs = ((need & ~FS_PAIR) == 0) ? FS_PAIR : ((need & ~FS_HINGE) == 0) ? FS_HINGE : FS_ALL;
+    }
+    n_w = (int64_t)P.var_w.size();
+    n_l = (int64_t)P.var_l.size();
+    nb_w = (n_w + (NT / 64) - 1) / (NT / 64);
+    zblocks = nb_w + (n_l + NT - 1) / NT;
+    n_slots = (int64_t)P.upos.size();
+    nz = (int64_t)z0.size();
+    xdelta = P.n_m;
+    admm_status s;
+    const int64_t pool_n = P.n_part + 2 * P.n_m;
+    if ((s = alloc(&pool, pool_n))) return s;
+    ADMM_HIP(hipMemset(pool, 0, (size_t)std::max<int64_t>(pool_n, 1) * sizeof(T)));
+    if ((s = put_conv(&par, P.par))) return s;
+    if ((s = put(&idx, P.idx))) return s;
+    if ((s = put(&bt, P.bt))) return s;
+    if ((s = alloc(&z[0], nz))) return s;
+    if ((s = alloc(&z[1], nz))) return s;
+    if ((s = put(&csr, P.csr))) return s;
+    if ((s = put(&var_w, P.var_w))) return s;
+    if ((s = put(&var_l, P.var_l))) return s;
+    if ((s = put(&rng_w, P.rng_w))) return s;
+    if ((s = put(&rng_l, P.rng_l))) return s;
+    if ((s = put_conv(&deg_w, P.deg_w))) return s;
+    if ((s = put_conv(&deg_l, P.deg_l))) return s;
+    if ((s = put(&upos, P.upos))) return s;
+    if ((s = put(&uz, P.uz))) return s;
+    if ((s = alloc(&bmx, xblocks))) return s;
+    if ((s = alloc(&bmz, zblocks))) return s;
+    io_n = std::max(n_slots, nz);
+    if ((s = alloc(&io, io_n))) return s;
+    return set_state(z0.data(), nullptr, nullptr);
+  }
+
+  admm_status set_state(const double* zh, const double* uh, hipStream_t st) override {
+    ADMM_HIP(hipSetDevice(device));
+    ADMM_HIP(hipMemcpyAsync(io, zh, nz * sizeof(double), hipMemcpyHostToDevice, st));
+    const int64_t gz = (nz + 255) / 256;
+    if (gz) convert_kernel<T><<<gz, 256, 0, st>>>(nz, io, z[zc]);
+    ADMM_HIP(hipGetLastError());
+    if (uh) {
+      ADMM_HIP(hipMemcpyAsync(io, uh, n_slots * sizeof(double), hipMemcpyHostToDevice, st));
+    }
+    const int64_t gs = (n_slots + 255) / 256;
+    if (gs)
+      set_state_kernel<T><<<gs, 256, 0, st>>>(n_slots, upos, uz, uh ? io : nullptr, z[zc], pool,
+                                              xdelta, 1);
+    ADMM_HIP(hipGetLastError());
+    ADMM_HIP(hipStreamSynchronize(st));
+    have_resid = false;
+    return ADMM_OK;
+  }
+
+  XArgs<T> xargs() const {
+    XArgs<T> a;
+    a.pool = pool;
+    a.idx = idx;
+    a.par = par;
+    a.z = z[zc];
+    a.blockmax = bmx;
+    a.bt = bt;
+    a.nb = nb;
+    a.alpha = alpha;
+    a.inv_rho = inv_rho;
+    return a;
+  }
+
+  template <bool A1, int FS>
+  void launch_x_fs(int mode, hipStream_t st) {
+    XArgs<T> a = xargs();
+    if (mode == PM_NORMAL)
+      xpass_kernel<T, A1, PM_NORMAL, FS><<<(unsigned)xblocks, NT, 0, st>>>(a);
+    else if (mode == PM_SAVE)
+      xpass_kernel<T, A1, PM_SAVE, FS><<<(unsigned)xblocks, NT, 0, st>>>(a);
+    else
+      xpass_kernel<T, A1, PM_RESID, FS><<<(unsigned)xblocks, NT, 0, st>>>(a);
+  }
+
+  template <bool A1>
+  void launch_x(int mode, hipStream_t st) {
+    if (fs == FS_PAIR) launch_x_fs<A1, FS_PAIR>(mode, st);
+    else if (fs == FS_HINGE) launch_x_fs<A1, FS_HINGE>(mode, st);
+    else launch_x_fs<A1, FS_ALL>(mode, st);
+  }
+
+  void launch_z(int check, hipStream_t st) {
+    ZArgs<T> a;
+    a.pool = pool;
+    a.csr = csr;
+    a.var_w = var_w;
+    a.rng_w = rng_w;
+    a.deg_w = deg_w;
+    a.n_w = n_w;
+    a.nb_w = (int32_t)nb_w;
+    a.var_l = var_l;
+    a.rng_l = rng_l;
+    a.deg_l = deg_l;
+    a.n_l = n_l;
+    a.zin = z[zc];
+    a.zout = z[zc ^ 1];
+    a.blockmax = bmz;
+    a.check = check;
+    if (zblocks) zpass_kernel<T><<<(unsigned)zblocks, NT, 0, st>>>(a);
+    zc ^= 1;
+  }
+
+  admm_status run(int32_t iters, hipStream_t st) override {
+    if (iters <= 0) return ADMM_OK;
+    ADMM_HIP(hipSetDevice(device));
+    for (int32_t k = 0; k < iters; ++k) {
+      const bool last = (k == iters - 1);
+      if (xblocks) {
+        if (alpha1) launch_x<true>(last ? PM_SAVE : PM_NORMAL, st);
+        else launch_x<false>(PM_NORMAL, st);
+      }
+      launch_z(last ? 1 : 0, st);
+    }
+    if (xblocks) {
+      if (alpha1) launch_x<true>(PM_RESID, st);
+      else launch_x<false>(PM_RESID, st);
+    }
+    ADMM_HIP(hipGetLastError());
+    have_resid = true;
+    return ADMM_OK;
+  }
+
+  // Same launches as run(), with an event pair around every kernel; returns
+  // the summed x-pass and z-pass durations in milliseconds (synchronises).
+  admm_status run_profiled(int32_t iters, hipStream_t st, double* x_ms, double* z_ms) override {
+    *x_ms = 0.0;
+    *z_ms = 0.0;
+    if (iters <= 0) return ADMM_OK;
+    ADMM_HIP(hipSetDevice(device));
+    std::vector<hipEvent_t> ev(4 * (size_t)iters);
+    for (auto& e : ev) ADMM_HIP(hipEventCreate(&e));
+    admm_status rc = ADMM_OK;
+    for (int32_t k = 0; k < iters; ++k) {
+      const bool last = (k == iters - 1);
+      hipEventRecord(ev[4 * k + 0], st);
+      if (xblocks) {
+        if (alpha1) launch_x<true>(last ? PM_SAVE : PM_NORMAL, st);
+        else launch_x<false>(PM_NORMAL, st);
+      }
+      hipEventRecord(ev[4 * k + 1], st);
+      hipEventRecord(ev[4 * k + 2], st);
+      launch_z(last ? 1 : 0, st);
+      hipEventRecord(ev[4 * k + 3], st);
+    }
+    if (xblocks) {
+      if (alpha1) launch_x<true>(PM_RESID, st);
+      else launch_x<false>(PM_RESID, st);
+    }
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) rc = admmi::set_err(ADMM_E_HIP, "profiled run: %s", hipGetErrorString(e));
+    for (int32_t k = 0; rc == ADMM_OK && k < iters; ++k) {
+      float a = 0.f, b = 0.f;
+      hipEventElapsedTime(&a, ev[4 * k + 0], ev[4 * k + 1]);
+      hipEventElapsedTime(&b, ev[4 * k + 2], ev[4 * k + 3]);
+      *x_ms += a;
+      *z_ms += b;
+    }
+    for (auto& ee : ev) hipEventDestroy(ee);
+    have_resid = (rc == ADMM_OK);
+    return rc;
+  }
+
+  admm_status get_z(double* out, hipStream_t st) override {
+    ADMM_HIP(hipSetDevice(device));
+    const int64_t g = (nz + 255) / 256;
+    if (g) widen_kernel<T><<<g, 256, 0, st>>>(nz, z[zc], io);
+    ADMM_HIP(hipGetLastError());
+    ADMM_HIP(hipMemcpyAsync(out, io, nz * sizeof(double), hipMemcpyDeviceToHost, st));
+    ADMM_HIP(hipStreamSynchronize(st));
+    return ADMM_OK;
+  }
+
+  admm_status get_slots(double* out, int which, hipStream_t st) override {
+    ADMM_HIP(hipSetDevice(device));
+    const int64_t g = (n_slots + 255) / 256;
+    if (g) {
+      if (alpha1)
+        get_slots_kernel<T, true><<<g, 256, 0, st>>>(n_slots, upos, uz, pool, z[zc], xdelta, alpha,
+                                                      which, io);
+      else
+        get_slots_kernel<T, false><<<g, 256, 0, st>>>(n_slots, upos, uz, pool, z[zc], xdelta,
+                                                       alpha, which, io);
+    }
+    ADMM_HIP(hipGetLastError());
+    ADMM_HIP(hipMemcpyAsync(out, io, n_slots * sizeof(double), hipMemcpyDeviceToHost, st));
+    ADMM_HIP(hipStreamSynchronize(st));
+    return ADMM_OK;
+  }
+
+  admm_status residuals(double* r, double* s, hipStream_t st) override {
+    if (!have_resid) return admmi::set_err(ADMM_E_STATE, "no iteration has been run since the last state change");
+    ADMM_HIP(hipSetDevice(device));
+    std::vector<T> hx(std::max<int64_t>(xblocks, 1), T(0)), hz(std::max<int64_t>(zblocks, 1), T(0));
+    if (xblocks) ADMM_HIP(hipMemcpyAsync(hx.data(), bmx, xblocks * sizeof(T), hipMemcpyDeviceToHost, st));
+    if (zblocks) ADMM_HIP(hipMemcpyAsync(hz.data(), bmz, zblocks * sizeof(T), hipMemcpyDeviceToHost, st));
+    ADMM_HIP(hipStreamSynchronize(st));
+    T a = T(0), b = T(0);
+    for (T v : hx) a = std::max(a, v);
+    for (T v : hz) b = std::max(b, v);
+    *r = (double)a;
+    *s = (double)b / (double)inv_rho;
+    return ADMM_OK;
+  }
+
+  void* z_ptr() override { return z[zc]; }
+};
+
+admm_status check_graph(admm_graph* g) {
+  if (!g) return admmi::set_err(ADMM_E_ARG, "graph handle is NULL");
+  return ADMM_OK;
+}
+
+admm_status check_ready(admm_graph* g) {
+  if (!g) return admmi::set_err(ADMM_E_ARG, "graph handle is NULL");
+  if (g->state != 2) return admmi::set_err(ADMM_E_STATE, "graph is not finalized on a device");
+  return ADMM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+admm_status admm_graph_create(int32_t n_vars, const int32_t* var_dim, int32_t precision,
+                              admm_graph** out) {
+  admmi::clear_err();
+  if (!out) return admmi::set_err(ADMM_E_ARG, "out is NULL");
+  *out = nullptr;
+  if (n_vars < 0 || (n_vars > 0 && !var_dim)) return admmi::set_err(ADMM_E_ARG, "bad variable list");
+  if (precision != ADMM_FP32 && precision != ADMM_FP64)
+    return admmi::set_err(ADMM_E_ARG, "precision must be ADMM_FP32 or ADMM_FP64");
+  std::unique_ptr<admm_graph> g(new admm_graph());
+  g->precision = precision;
+  g->dim.assign(var_dim, var_dim + n_vars);
+  g->zoff.resize(n_vars);
+  int64_t off = 0;
+  for (int32_t i = 0; i < n_vars; ++i) {
+    if (var_dim[i] < 1) return admmi::set_err(ADMM_E_ARG, "variable %d has dimension %d < 1", i, var_dim[i]);
+    g->zoff[i] = off;
+    off += var_dim[i];
+  }
+  if (off > 0x7fffffffLL) return admmi::set_err(ADMM_E_UNSUPPORTED, "more than 2^31 scalars in z");
+  g->nz = off;
+  *out = g.release();
+  return ADMM_OK;
+}
+
+admm_status admm_graph_add_factors(admm_graph* g, int32_t kind, int32_t n_factors, int32_t arity,
+                                   const int32_t* var_ids, const double* params, int32_t param_len,
+                                   int32_t shared_params) {
+  admmi::clear_err();
+  if (admm_status s = check_graph(g)) return s;
+  if (g->state != 0) return admmi::set_err(ADMM_E_STATE, "graph already finalized");
+  if (kind < KD_NONOVERLAP || kind > KD_LINDYN0) return admmi::set_err(ADMM_E_ARG, "unknown factor kind %d", kind);
+  if (n_factors < 0 || arity < 1 || param_len < 0) return admmi::set_err(ADMM_E_ARG, "bad sizes");
+  if (n_factors > 0 && !var_ids) return admmi::set_err(ADMM_E_ARG, "var_ids is NULL");
+  if (param_len > 0 && !params) return admmi::set_err(ADMM_E_ARG, "params is NULL");
+  Group gr;
+  gr.kind = kind;
+  gr.n = n_factors;
+  gr.arity = arity;
+  gr.plen = param_len;
+  gr.shared = shared_params != 0;
+  gr.vids.assign(var_ids, var_ids + (int64_t)n_factors * arity);
+  int64_t slots = 0;
+  for (int64_t i = 0; i < (int64_t)gr.vids.size(); ++i) {
+    const int32_t v = gr.vids[i];
+    if (v < 0 || v >= (int32_t)g->dim.size())
+      return admmi::set_err(ADMM_E_ARG, "variable id %d out of range [0,%d)", v, (int)g->dim.size());
+    slots += g->dim[v];
+  }
+  for (int64_t f = 0; f < n_factors; ++f)
+    for (int e = 0; e < arity; ++e)
+      for (int e2 = e + 1; e2 < arity; ++e2)
+        if (gr.vids[f * arity + e] == gr.vids[f * arity + e2])
+          return admmi::set_err(ADMM_E_ARG, "factor %lld lists variable %d twice", (long long)f,
+                                gr.vids[f * arity + e]);
+  const int64_t np = gr.shared ? param_len : (int64_t)n_factors * param_len;
+  if (np) gr.params.assign(params, params + np);
+  {
+    std::string why;
+    int32_t nn = 0, mm = 0;
+    if (!kind_dim_ok(*g, gr, why, nn, mm)) return admmi::set_err(ADMM_E_ARG, "%s", why.c_str());
+  }
+  g->n_factors += n_factors;
+  g->n_edges += (int64_t)n_factors * arity;
+  g->n_slots += slots;
+  g->groups.push_back(std::move(gr));
+  return ADMM_OK;
+}
+
+admm_status admm_graph_set_rho(admm_graph* g, double rho) {
+  admmi::clear_err();
+  if (admm_status s = check_graph(g)) return s;
+  if (g->state != 0) return admmi::set_err(ADMM_E_STATE, "graph already finalized");
+  if (!(rho > 0.0) || !std::isfinite(rho)) return admmi::set_err(ADMM_E_ARG, "rho must be > 0");
+  g->rho = rho;
+  return ADMM_OK;
+}
+
+admm_status admm_graph_set_alpha(admm_graph* g, double alpha) {
+  admmi::clear_err();
+  if (admm_status s = check_graph(g)) return s;
+  if (g->state != 0) return admmi::set_err(ADMM_E_STATE, "graph already finalized");
+  if (!(alpha > 0.0) || !std::isfinite(alpha)) return admmi::set_err(ADMM_E_ARG, "alpha must be > 0");
+  g->alpha = alpha;
+  return ADMM_OK;
+}
+
+admm_status admm_graph_finalize(admm_graph* g, int32_t device) {
+  admmi::clear_err();
+  if (admm_status s = check_graph(g)) return s;
+  if (g->state == 2) return admmi::set_err(ADMM_E_STATE, "graph already finalized");
+  if (admm_status s = build_plan(*g, g->plan)) return s;
+  const Plan& P = g->plan;
+  const int64_t es = g->precision == ADMM_FP64 ? 8 : 4;
+  admm_graph_info& I = g->info;
+  I.n_vars = (int64_t)g->dim.size();
+  I.n_scalars = g->nz;
+  I.n_factors = g->n_factors;
+  I.n_edges = g->n_edges;
+  I.n_slots = g->n_slots;
+  I.n_buckets = (int64_t)P.bt.size();
+  I.n_pair_tiles = P.n_pair_tiles;
+  I.n_contributions = (int64_t)P.csr.size();
+  I.precision = g->precision;
+  I.alpha_is_one = g->alpha == 1.0;
+  I.state_bytes = (P.n_part + 2 * P.n_m) * es;
+  // algorithmic: state read + write per slot (m; plus x when alpha != 1) and
+  // per-factor prox data; layout: indices, partial sums and their reads.
+  I.algo_bytes_per_iter = P.algo_elems * es * (g->alpha == 1.0 ? 1 : 2);
+  I.layout_bytes_per_iter = P.layout_elems * es + P.layout_idx_bytes;
+  if (admm_status s = admmi::probe_device(device)) {
+    g->state = 1;
+    return s;
+  }
+  ADMM_HIP(hipSetDevice(device));
+  std::unique_ptr<EngineBase> eng;
+  if (g->precision == ADMM_FP64) {
+    auto* e = new Engine<double>();
+    e->device = device;
+    eng.reset(e);
+  } else {
+    auto* e = new Engine<float>();
+    e->device = device;
+    eng.reset(e);
+  }
+  std::vector<double> z0(g->nz, 0.0);
+  if (admm_status s = eng->upload(P, z0, g->rho, g->alpha)) return s;
+  g->eng = std::move(eng);
+  g->device = device;
+  g->state = 2;
+  // host copies only needed for the layout; keep user slot map on device only
+  g->plan.idx.clear(); g->plan.idx.shrink_to_fit();
+  g->plan.par.clear(); g->plan.par.shrink_to_fit();
+  g->plan.csr.clear(); g->plan.csr.shrink_to_fit();
+  g->plan.upos.clear(); g->plan.upos.shrink_to_fit();
+  g->plan.uz.clear(); g->plan.uz.shrink_to_fit();
+  return ADMM_OK;
+}
+
+admm_status admm_graph_info_get(const admm_graph* g, admm_graph_info* info) {
+  admmi::clear_err();
+  if (!g || !info) return admmi::set_err(ADMM_E_ARG, "NULL argument");
+  if (g->state == 0) return admmi::set_err(ADMM_E_STATE, "graph not finalized");
+  *info = g->info;
+  return ADMM_OK;
+}
+
+admm_status admm_set_state(admm_graph* g, const double* z, const double* u, void* stream) {
+  admmi::clear_err();
+  if (admm_status s = check_ready(g)) return s;
+  if (!z) return admmi::set_err(ADMM_E_ARG, "z is NULL");
+  return g->eng->set_state(z, u, (hipStream_t)stream);
+}
+
+admm_status admm_run(admm_graph* g, int32_t iters, void* stream) {
+  admmi::clear_err();
+  if (admm_status s = check_ready(g)) return s;
+  if (iters < 0) return admmi::set_err(ADMM_E_ARG, "iters < 0");
+  return g->eng->run(iters, (hipStream_t)stream);
+}
+
+admm_status admm_run_profiled(admm_graph* g, int32_t iters, void* stream, double* xpass_ms,
+                              double* zpass_ms) {
+  admmi::clear_err();
+  if (admm_status s = check_ready(g)) return s;
+  if (iters < 0 || !xpass_ms || !zpass_ms) return admmi::set_err(ADMM_E_ARG, "bad arguments");
+  return g->eng->run_profiled(iters, (hipStream_t)stream, xpass_ms, zpass_ms);
+}
+
+admm_status admm_get_z(admm_graph* g, double* z, void* stream) {
+  admmi::clear_err();
+  if (admm_status s = check_ready(g)) return s;
+  if (!z) return admmi::set_err(ADMM_E_ARG, "z is NULL");
+  return g->eng->get_z(z, (hipStream_t)stream);
+}
+
+admm_status admm_get_u(admm_graph* g, double* u, void* stream) {
+  admmi::clear_err();
+  if (admm_status s = check_ready(g)) return s;
+  if (!u) return admmi::set_err(ADMM_E_ARG, "u is NULL");
+  return g->eng->get_slots(u, 0, (hipStream_t)stream);
+}
+
+admm_status admm_get_x(admm_graph* g, double* x, void* stream) {
+  admmi::clear_err();
+  if (admm_status s = check_ready(g)) return s;
+  if (!x) return admmi::set_err(ADMM_E_ARG, "x is NULL");
+  return g->eng->get_slots(x, 1, (hipStream_t)stream);
+}
+
+admm_status admm_get_residuals(admm_graph* g, double* r, double* s, void* stream) {
+  admmi::clear_err();
+  if (admm_status st = check_ready(g)) return st;
+  if (!r || !s) return admmi::set_err(ADMM_E_ARG, "NULL output");
+  return g->eng->residuals(r, s, (hipStream_t)stream);
+}
+
+admm_status admm_z_device_ptr(admm_graph* g, void** z_dev) {
+  admmi::clear_err();
+  if (admm_status s = check_ready(g)) return s;
+  if (!z_dev) return admmi::set_err(ADMM_E_ARG, "NULL output");
+  *z_dev = g->eng->z_ptr();
+  return ADMM_OK;
+}
+
+admm_status admm_graph_destroy(admm_graph* g) {
+  admmi::clear_err();
+  delete g;
+  return ADMM_OK;
+}
+
+}  // extern "C"

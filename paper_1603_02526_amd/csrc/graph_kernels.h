@@ -1,0 +1,715 @@
+// Device side of the factor-graph ADMM engine (gfx950, wave64).
+//
+// One iteration of Algorithm 2 (paper Sec. II) is two launches:
+//   x-pass  one fused launch over every factor bucket.  Per edge slot it
+//           reads the persistent state, forms u and n = z - u, applies the
+//           bucket's proximal operator (eq. (3), appendix closed forms),
+//           forms m = x + u and writes the new state.  Structured buckets
+//           also emit per-tile partial sums of m for the z-update.
+//   z-pass  z_b = (sum of the contributions listed for b) / deg(b), summed
+//           in a fixed order (one lane per short list, a wavefront tree per
+//           long list): deterministic, no atomics.
+// State per slot: with alpha == 1 only m is kept (u = m - z, n = 2z - m);
+// otherwise m and x are kept and u = (m - x) + alpha (x - z).
+#pragma once
+
+#include "internal.h"
+
+namespace admmg {
+
+constexpr int NT = 256;              // threads per workgroup, every pass
+constexpr int PB = 64;               // entity block of dense pair tiles
+constexpr int PR = PB * PB / NT;     // pair rows per thread
+constexpr int MAXN = 16;             // lindyn state dim limit (general path)
+constexpr int MAXM = 8;              // lindyn input dim limit (general path)
+constexpr int LANE_MAX = 4;          // z-lists up to this length: one lane
+
+enum BucketMode : int32_t {
+  BM_PAIR = 1,        // complete pairwise non-overlap, dense 64x64 tiles
+  BM_UNIF_HINGE = 2,  // hinge factors that all share one variable list
+  BM_GEN_FACTOR = 3,  // one thread per factor, per-edge z offsets
+  BM_GEN_SLOT = 4,    // separable prox: one thread per scalar slot
+};
+
+enum PassMode : int { PM_NORMAL = 0, PM_SAVE = 1, PM_RESID = 2 };
+
+enum Kind : int32_t {
+  KD_NONOVERLAP = 1, KD_WALL = 2, KD_RADIUS = 3, KD_QUAD = 4, KD_BOX = 5,
+  KD_HINGE = 6, KD_L2 = 7, KD_LINDYN = 8, KD_LINDYN0 = 9,
+};
+
+// Descriptor of one bucket, read by the x-pass from device memory.
+struct BucketDesc {
+  int32_t mode, kind;
+  int32_t blk0, blk1;   // x-pass workgroups [blk0, blk1)
+  int64_t n;            // factors (factor modes), slots (GEN_SLOT), tiles (PAIR)
+  int64_t nfp;          // SoA row stride
+  int32_t arity, nslot; // edges / scalar slots per factor
+  int32_t d, nn, mm, dmax;  // hinge d (and its register bound); lindyn n, m
+  int32_t E, NB;        // pair layout: entities, entity blocks
+  int64_t m_off, x_off, part_off;  // element offsets in the pool
+  int64_t idx_off;      // offset in the int32 index buffer
+  int64_t par_off;      // element offset in the parameter buffer
+};
+
+template <typename T>
+struct XArgs {
+  T* pool;
+  const int32_t* idx;
+  const T* par;
+  const T* z;
+  T* blockmax;
+  const BucketDesc* bt;
+  int32_t nb;
+  T alpha, inv_rho;
+};
+
+template <typename T>
+struct ZArgs {
+  const T* pool;
+  const uint32_t* csr;
+  const int32_t* var_w;
+  const int64_t* rng_w;
+  const T* deg_w;
+  int64_t n_w;
+  int32_t nb_w;
+  const int32_t* var_l;
+  const int64_t* rng_l;
+  const T* deg_l;
+  int64_t n_l;
+  const T* zin;
+  T* zout;
+  T* blockmax;
+  int32_t check;
+};
+
+template <typename T>
+__device__ __forceinline__ T tabs(T v) { return v < T(0) ? -v : v; }
+template <typename T>
+__device__ __forceinline__ T tmax(T a, T b) { return a > b ? a : b; }
+template <typename T>
+__device__ __forceinline__ T tmin(T a, T b) { return a < b ? a : b; }
+
+// Block-wide max of non-negative values, stored by thread 0.
+template <typename T>
+__device__ __forceinline__ void block_max_store(T v, T* out) {
+  __shared__ T red[NT / 64];
+  v = admmi::wave_max(v);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    T mx = red[0];
+#pragma unroll
+    for (int i = 1; i < NT / 64; ++i) mx = tmax(mx, red[i]);
+    out[blockIdx.x] = mx;
+  }
+}
+
+// u and n of one slot from the stored state.
+template <typename T, bool A1>
+__device__ __forceinline__ void state_un(T m, T xo, T zv, T alpha, T& u, T& n) {
+  if constexpr (A1) {
+    u = m - zv;
+  } else {
+    u = (m - xo) + alpha * (xo - zv);
+  }
+  n = zv - u;
+}
+
+// ---------------------------------------------------------------------------
+// Proximal operators in working precision (appendix closed forms).
+// ---------------------------------------------------------------------------
+
+// Non-overlap |c1 - c2| >= r1 + r2 with equal weights: move both centres
+// apart along n_hat and shrink both radii by D/4, D = max(0, r1+r2-|c2-c1|);
+// n_hat = (1,0) when the centres coincide.
+template <typename T>
+__device__ __forceinline__ void prox_nonoverlap(T* v) {
+  const T dx = v[3] - v[0], dy = v[4] - v[1];
+  const T L = sqrt(dx * dx + dy * dy);
+  const T D = v[2] + v[5] - L;
+  if (D > T(0)) {
+    T hx = T(1), hy = T(0);
+    if (L > T(0)) {
+      const T il = T(1) / L;
+      hx = dx * il;
+      hy = dy * il;
+    }
+    const T st = D * T(0.25);
+    v[0] -= st * hx;
+    v[1] -= st * hy;
+    v[2] -= st;
+    v[3] += st * hx;
+    v[4] += st * hy;
+    v[5] -= st;
+  }
+}
+
+// Wall Q^T(c - V) >= r; p = (Qx, Qy, Q.V, 1/(|Q|^2+1)).
+template <typename T>
+__device__ __forceinline__ void prox_wall(T* v, T qx, T qy, T qv, T ik) {
+  const T g = qx * v[0] + qy * v[1] - qv - v[2];
+  if (g < T(0)) {
+    const T st = -g * ik;
+    v[0] += st * qx;
+    v[1] += st * qy;
+    v[2] -= st;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Dense pairwise non-overlap tiles.  Tile (I, J), I <= J, holds the pairs
+// (I*64 + li, J*64 + lj); storage [slot 0..5][li*64 + lj] with slots
+// (c_i.x, c_i.y, r_i, c_j.x, c_j.y, r_j).  Thread t owns column lj = t % 64
+// and rows 16*(t/64) .. +15; rows are summed across the wavefront, columns
+// in registers and then across the four wavefronts.
+// Partials per tile: [row li][3] then [col lj][3].
+// ---------------------------------------------------------------------------
+template <typename T, bool A1, int MODE>
+__device__ __forceinline__ void xpass_pair(const XArgs<T>& a, const BucketDesc& b, int tile) {
+  __shared__ T zrow[PB * 3];
+  __shared__ T zcol[PB * 3];
+  __shared__ T cacc[NT / 64][PB * 3];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int32_t* tiles = a.idx + b.idx_off;
+  const int32_t* ent = tiles + 2 * b.n;
+  const int I = tiles[2 * tile], J = tiles[2 * tile + 1];
+  if (t < 2 * PB) {
+    const int l = t & (PB - 1);
+    const int e = ((t < PB) ? I : J) * PB + l;
+    T cx = T(0), cy = T(0), r = T(0);
+    if (e < b.E) {
+      const int zc = ent[2 * e], zr = ent[2 * e + 1];
+      cx = a.z[zc];
+      cy = a.z[zc + 1];
+      r = a.z[zr];
+    }
+    T* dst = (t < PB) ? zrow : zcol;
+    dst[l * 3 + 0] = cx;
+    dst[l * 3 + 1] = cy;
+    dst[l * 3 + 2] = r;
+  }
+  __syncthreads();
+  const int lj = lane;
+  const int ej = J * PB + lj;
+  const T zj0 = zcol[lj * 3 + 0], zj1 = zcol[lj * 3 + 1], zj2 = zcol[lj * 3 + 2];
+  constexpr int64_t TS = 6 * PB * PB;
+  T* mt = a.pool + b.m_off + (int64_t)tile * TS;
+  T* xt = a.pool + b.x_off + (int64_t)tile * TS;
+  T ca0 = T(0), ca1 = T(0), ca2 = T(0);
+  T rv0 = T(0), rv1 = T(0), rv2 = T(0);
+  T rmax = T(0);
+#pragma unroll
+  for (int k = 0; k < PR; ++k) {
+    const int li = w * PR + k;
+    const int ei = I * PB + li;
+    const bool valid = (ei < b.E) && (ej < b.E) && (I != J || li < lj);
+    const int p = li * PB + lj;
+    const T zz[6] = {zrow[li * 3 + 0], zrow[li * 3 + 1], zrow[li * 3 + 2], zj0, zj1, zj2};
+    T mv[6];
+#pragma unroll
+    for (int s = 0; s < 6; ++s) mv[s] = mt[s * PB * PB + p];
+    if constexpr (MODE == PM_RESID) {
+#pragma unroll
+      for (int s = 0; s < 6; ++s) {
+        const T xv = xt[s * PB * PB + p];
+        if (valid) rmax = tmax(rmax, tabs(xv - zz[s]));
+      }
+    } else {
+      T u[6], v[6];
+#pragma unroll
+      for (int s = 0; s < 6; ++s) {
+        T xo = T(0);
+        if constexpr (!A1) xo = xt[s * PB * PB + p];
+        state_un<T, A1>(mv[s], xo, zz[s], a.alpha, u[s], v[s]);
+      }
+      prox_nonoverlap(v);
+      T mn[6];
+#pragma unroll
+      for (int s = 0; s < 6; ++s) mn[s] = v[s] + u[s];
+      if (valid) {
+#pragma unroll
+        for (int s = 0; s < 6; ++s) {
+          mt[s * PB * PB + p] = mn[s];
+          if constexpr (!A1 || MODE == PM_SAVE) xt[s * PB * PB + p] = v[s];
+        }
+      }
+      ca0 += valid ? mn[3] : T(0);
+      ca1 += valid ? mn[4] : T(0);
+      ca2 += valid ? mn[5] : T(0);
+      const T r0 = admmi::wave_sum(valid ? mn[0] : T(0));
+      const T r1 = admmi::wave_sum(valid ? mn[1] : T(0));
+      const T r2 = admmi::wave_sum(valid ? mn[2] : T(0));
+      if (lane == k) {
+        rv0 = r0;
+        rv1 = r1;
+        rv2 = r2;
+      }
+    }
+  }
+  if constexpr (MODE == PM_RESID) {
+    block_max_store(rmax, a.blockmax);
+  } else {
+    T* part = a.pool + b.part_off + (int64_t)tile * (6 * PB);
+    if (lane < PR) {
+      const int li = w * PR + lane;
+      part[li * 3 + 0] = rv0;
+      part[li * 3 + 1] = rv1;
+      part[li * 3 + 2] = rv2;
+    }
+    cacc[w][lj * 3 + 0] = ca0;
+    cacc[w][lj * 3 + 1] = ca1;
+    cacc[w][lj * 3 + 2] = ca2;
+    __syncthreads();
+    if (t < PB * 3) {
+      T s = cacc[0][t];
+#pragma unroll
+      for (int q = 1; q < NT / 64; ++q) s += cacc[q][t];
+      part[3 * PB + t] = s;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Hinge factor C max(0, 1 - y(w.a + b)) over scalar edges (w_1..w_d, b).
+// Parameters SoA [d+3][nfp]: y*a_1..y*a_d, y, C, rho/(|a|^2+1).
+// UNIF: every factor shares the variable list (z offsets [d+1]); each
+// workgroup of 256 factors emits column partials [tile][d+1].
+// Otherwise z offsets are per edge [d+1][nfp] and m itself is summed.
+// ---------------------------------------------------------------------------
+template <typename T, bool A1, int MODE, bool UNIF, int DM>
+__device__ __forceinline__ void xpass_hinge(const XArgs<T>& a, const BucketDesc& b, int blk) {
+  __shared__ T wsum[NT / 64][DM + 1];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int d = b.d;
+  const int64_t f = (int64_t)blk * NT + t;
+  const bool valid = f < b.n;
+  const int64_t ff = valid ? f : 0;
+  const int64_t nfp = b.nfp;
+  const int32_t* zo = a.idx + b.idx_off;
+  const T* P = a.par + b.par_off;
+  T* M = a.pool + b.m_off;
+  T* X = a.pool + b.x_off;
+  T nv[DM], uv[DM], ya[DM];
+  T dot = T(0);
+  T rmax = T(0);
+#pragma unroll
+  for (int k = 0; k < DM; ++k) {
+    if (k < d) {
+      const T zk = UNIF ? a.z[zo[k]] : a.z[zo[k * nfp + ff]];
+      const T mk = M[k * nfp + ff];
+      T xo = T(0);
+      if constexpr (!A1 || MODE == PM_RESID) xo = X[k * nfp + ff];
+      if constexpr (MODE == PM_RESID) {
+        if (valid) rmax = tmax(rmax, tabs(xo - zk));
+      } else {
+        state_un<T, A1>(mk, xo, zk, a.alpha, uv[k], nv[k]);
+        ya[k] = P[k * nfp + ff];
+        dot += nv[k] * ya[k];
+      }
+    }
+  }
+  const T zb = UNIF ? a.z[zo[d]] : a.z[zo[d * nfp + ff]];
+  const T mb = M[d * nfp + ff];
+  T xob = T(0);
+  if constexpr (!A1 || MODE == PM_RESID) xob = X[d * nfp + ff];
+  if constexpr (MODE == PM_RESID) {
+    if (valid) rmax = tmax(rmax, tabs(xob - zb));
+    block_max_store(rmax, a.blockmax);
+    return;
+  } else {
+    T ub, nb;
+    state_un<T, A1>(mb, xob, zb, a.alpha, ub, nb);
+    const T y = P[d * nfp + ff], C = P[(d + 1) * nfp + ff], iD = P[(d + 2) * nfp + ff];
+    dot += y * nb;
+    const T tau = tmin(C, tmax(T(0), (T(1) - dot) * iD));
+    const T st = tau * a.inv_rho;
+    const T xb = nb + st * y;
+    const T mnb = xb + ub;
+    if (valid) {
+      M[d * nfp + ff] = mnb;
+      if constexpr (!A1 || MODE == PM_SAVE) X[d * nfp + ff] = xb;
+    }
+#pragma unroll
+    for (int k = 0; k < DM; ++k) {
+      if (k < d) {
+        const T xk = nv[k] + st * ya[k];
+        const T mk = xk + uv[k];
+        if (valid) {
+          M[k * nfp + ff] = mk;
+          if constexpr (!A1 || MODE == PM_SAVE) X[k * nfp + ff] = xk;
+        }
+        if constexpr (UNIF) {
+          const T s = admmi::wave_sum(valid ? mk : T(0));
+          if (lane == 0) wsum[w][k] = s;
+        }
+      }
+    }
+    if constexpr (UNIF) {
+      const T s = admmi::wave_sum(valid ? mnb : T(0));
+      if (lane == 0) wsum[w][d] = s;
+      __syncthreads();
+      if (t <= d) {
+        T acc = wsum[0][t];
+#pragma unroll
+        for (int q = 1; q < NT / 64; ++q) acc += wsum[q][t];
+        a.pool[b.part_off + (int64_t)blk * (d + 1) + t] = acc;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Separable operators, one thread per scalar slot.  Params [2][nfp]:
+//   RADIUS  x = max(0, p0 n), p0 = rho/(rho - gamma)
+//   QUAD    x = p0 n,         p0 = rho/(rho + q_k)
+//   L2      x = p0 n,         p0 = rho/(rho + lambda)
+//   BOX     x = min(p1, max(p0, n)), (p0, p1) = (lo, hi)
+// ---------------------------------------------------------------------------
+template <typename T, bool A1, int MODE>
+__device__ __forceinline__ void xpass_slot(const XArgs<T>& a, const BucketDesc& b, int blk) {
+  const int64_t s = (int64_t)blk * NT + threadIdx.x;
+  T rmax = T(0);
+  if (s < b.n) {
+    const int32_t* zi = a.idx + b.idx_off;
+    const T* P = a.par + b.par_off;
+    T* M = a.pool + b.m_off;
+    T* X = a.pool + b.x_off;
+    const T zv = a.z[zi[s]];
+    if constexpr (MODE == PM_RESID) {
+      rmax = tabs(X[s] - zv);
+    } else {
+      T xo = T(0);
+      if constexpr (!A1) xo = X[s];
+      T u, n;
+      state_un<T, A1>(M[s], xo, zv, a.alpha, u, n);
+      const T p0 = P[s];
+      T x;
+      if (b.kind == KD_BOX) {
+        x = tmin(P[b.nfp + s], tmax(p0, n));
+      } else if (b.kind == KD_RADIUS) {
+        x = tmax(T(0), p0 * n);
+      } else {
+        x = p0 * n;
+      }
+      M[s] = x + u;
+      if constexpr (!A1 || MODE == PM_SAVE) X[s] = x;
+    }
+  }
+  if constexpr (MODE == PM_RESID) block_max_store(rmax, a.blockmax);
+}
+
+// ---------------------------------------------------------------------------
+// General factor buckets, one thread per factor, explicit per-edge z offsets
+// [edge][nfp].  Register arrays have compile-time sizes so nothing spills.
+// ---------------------------------------------------------------------------
+
+// Gather u and n for a factor whose edge e has dimension dims[e].
+template <typename T, bool A1, int MODE, int NSL>
+__device__ __forceinline__ void gen_gather(const XArgs<T>& a, const BucketDesc& b, int64_t f,
+                                           const int (&dims)[4], int arity, T (&u)[NSL],
+                                           T (&v)[NSL], T& rmax) {
+  const int64_t nfp = b.nfp;
+  const int32_t* zo = a.idx + b.idx_off;
+  const T* M = a.pool + b.m_off;
+  const T* X = a.pool + b.x_off;
+  int s = 0;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    if (e < arity) {
+      const int z0 = zo[e * nfp + f];
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        if (c < dims[e]) {
+          const T zv = a.z[z0 + c];
+          const T mv = M[s * nfp + f];
+          T xo = T(0);
+          if constexpr (!A1 || MODE == PM_RESID) xo = X[s * nfp + f];
+          if constexpr (MODE == PM_RESID) {
+            rmax = tmax(rmax, tabs(xo - zv));
+          } else {
+            state_un<T, A1>(mv, xo, zv, a.alpha, u[s], v[s]);
+          }
+          ++s;
+        }
+      }
+    }
+  }
+}
+
+template <typename T, bool A1, int MODE, int NSL>
+__device__ __forceinline__ void gen_store(const XArgs<T>& a, const BucketDesc& b, int64_t f,
+                                          const T (&u)[NSL], const T (&v)[NSL]) {
+  T* M = a.pool + b.m_off;
+  T* X = a.pool + b.x_off;
+#pragma unroll
+  for (int s = 0; s < NSL; ++s) {
+    M[s * b.nfp + f] = v[s] + u[s];
+    if constexpr (!A1 || MODE == PM_SAVE) X[s * b.nfp + f] = v[s];
+  }
+}
+
+// Non-overlap and wall factors on arbitrary variables.
+template <typename T, bool A1, int MODE>
+__device__ __forceinline__ void xpass_geom(const XArgs<T>& a, const BucketDesc& b, int blk) {
+  const int64_t f = (int64_t)blk * NT + threadIdx.x;
+  T rmax = T(0);
+  if (f < b.n) {
+    if (b.kind == KD_NONOVERLAP) {
+      const int dims[4] = {2, 1, 2, 1};
+      T u[6], v[6];
+      gen_gather<T, A1, MODE, 6>(a, b, f, dims, 4, u, v, rmax);
+      if constexpr (MODE != PM_RESID) {
+        prox_nonoverlap(v);
+        gen_store<T, A1, MODE, 6>(a, b, f, u, v);
+      }
+    } else {
+      const int dims[4] = {2, 1, 0, 0};
+      T u[3], v[3];
+      gen_gather<T, A1, MODE, 3>(a, b, f, dims, 2, u, v, rmax);
+      if constexpr (MODE != PM_RESID) {
+        const T* P = a.par + b.par_off;
+        const int64_t nfp = b.nfp;
+        prox_wall(v, P[f], P[nfp + f], P[2 * nfp + f], P[3 * nfp + f]);
+        gen_store<T, A1, MODE, 3>(a, b, f, u, v);
+      }
+    }
+  }
+  if constexpr (MODE == PM_RESID) block_max_store(rmax, a.blockmax);
+}
+
+// Linear-dynamics projections, one thread per factor.
+//   LINDYN  edges (x, u, x'), params [M = [A B] (n x (n+m)), S = (I+MM^T)^-1]:
+//           v = S (M a - x'), a <- a - M^T v, x' <- x' + v, a = (x, u).
+//   LINDYN0 edges (u, x'), params [B (n x m), S0 = (I+BB^T)^-1, c = A x0]:
+//           v = S0 (B u + c - x'), u <- u - B^T v, x' <- x' + v.
+// Slot s of the factor is stored at [s][nfp]; a occupies slots [0, k), x'
+// slots [k, k+n).
+template <typename T, bool A1, int MODE>
+__device__ __forceinline__ void xpass_lindyn(const XArgs<T>& a, const BucketDesc& b, int blk) {
+  constexpr int MK = MAXN + MAXM;
+  const int64_t f = (int64_t)blk * NT + threadIdx.x;
+  T rmax = T(0);
+  if (f < b.n) {
+    const int64_t nfp = b.nfp;
+    const int32_t* zo = a.idx + b.idx_off;
+    T* M = a.pool + b.m_off;
+    T* X = a.pool + b.x_off;
+    const bool first = (b.kind == KD_LINDYN0);
+    const int n = b.nn, m = b.mm;
+    const int k = first ? m : n + m;
+    // z offset of slot s: edges (x, u, x') or (u, x')
+    const int zx = first ? 0 : zo[f];
+    const int zu = first ? zo[f] : zo[nfp + f];
+    const int zx1 = first ? zo[nfp + f] : zo[2 * nfp + f];
+    T ua[MK], va[MK], ub[MAXN], vb[MAXN];
+#pragma unroll
+    for (int j = 0; j < MK; ++j) {
+      if (j < k) {
+        const int zi = first ? (zu + j) : (j < n ? zx + j : zu + (j - n));
+        const T zv = a.z[zi];
+        T xo = T(0);
+        if constexpr (!A1 || MODE == PM_RESID) xo = X[j * nfp + f];
+        if constexpr (MODE == PM_RESID) {
+          rmax = tmax(rmax, tabs(xo - zv));
+        } else {
+          state_un<T, A1>(M[j * nfp + f], xo, zv, a.alpha, ua[j], va[j]);
+        }
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < MAXN; ++r) {
+      if (r < n) {
+        const T zv = a.z[zx1 + r];
+        T xo = T(0);
+        if constexpr (!A1 || MODE == PM_RESID) xo = X[(k + r) * nfp + f];
+        if constexpr (MODE == PM_RESID) {
+          rmax = tmax(rmax, tabs(xo - zv));
+        } else {
+          state_un<T, A1>(M[(k + r) * nfp + f], xo, zv, a.alpha, ub[r], vb[r]);
+        }
+      }
+    }
+    if constexpr (MODE != PM_RESID) {
+      const T* P = a.par + b.par_off + zo[b.arity * nfp + f];
+      const T* Mx = P;
+      const T* S = P + n * k;
+      const T* cc = S + n * n;
+      T wv[MAXN], vv[MAXN];
+#pragma unroll
+      for (int r = 0; r < MAXN; ++r) {
+        if (r < n) {
+          T s = first ? (cc[r] - vb[r]) : -vb[r];
+#pragma unroll
+          for (int j = 0; j < MK; ++j)
+            if (j < k) s += Mx[r * k + j] * va[j];
+          wv[r] = s;
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < MAXN; ++r) {
+        if (r < n) {
+          T s = T(0);
+#pragma unroll
+          for (int j = 0; j < MAXN; ++j)
+            if (j < n) s += S[r * n + j] * wv[j];
+          vv[r] = s;
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < MK; ++j) {
+        if (j < k) {
+          T s = T(0);
+#pragma unroll
+          for (int r = 0; r < MAXN; ++r)
+            if (r < n) s += Mx[r * k + j] * vv[r];
+          va[j] -= s;
+          M[j * nfp + f] = va[j] + ua[j];
+          if constexpr (!A1 || MODE == PM_SAVE) X[j * nfp + f] = va[j];
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < MAXN; ++r) {
+        if (r < n) {
+          vb[r] += vv[r];
+          M[(k + r) * nfp + f] = vb[r] + ub[r];
+          if constexpr (!A1 || MODE == PM_SAVE) X[(k + r) * nfp + f] = vb[r];
+        }
+      }
+    }
+  }
+  if constexpr (MODE == PM_RESID) block_max_store(rmax, a.blockmax);
+}
+
+// Feature sets compiled into one x-pass kernel; the host picks the
+// smallest set that covers a graph's buckets, so the register budget of a
+// launch is that of the paths it can take.
+enum Features : int {
+  FT_PAIR = 1,     // dense pair tiles
+  FT_UHINGE = 2,   // shared-variable hinge, d <= 32
+  FT_GEN = 4,      // non-overlap/wall on arbitrary variables, separable slots
+  FT_WIDE = 8,     // hinge with d <= 64, general hinge, linear dynamics
+};
+constexpr int FS_PAIR = FT_PAIR | FT_GEN;
+constexpr int FS_HINGE = FT_UHINGE | FT_GEN;
+constexpr int FS_ALL = FT_PAIR | FT_UHINGE | FT_GEN | FT_WIDE;
+
+template <typename T, bool A1, int MODE, int FS>
+__global__ __launch_bounds__(NT) void xpass_kernel(XArgs<T> a) {
+  const int blk = blockIdx.x;
+  int bi = 0;
+  while (bi + 1 < a.nb && blk >= a.bt[bi].blk1) ++bi;
+  const BucketDesc b = a.bt[bi];
+  const int local = blk - b.blk0;
+  if ((FS & FT_PAIR) && b.mode == BM_PAIR) {
+    xpass_pair<T, A1, MODE>(a, b, local);
+  } else if ((FS & (FT_UHINGE | FT_WIDE)) && b.mode == BM_UNIF_HINGE) {
+    if ((FS & FT_UHINGE) && b.dmax <= 32)
+      xpass_hinge<T, A1, MODE, true, 32>(a, b, local);
+    else if (FS & FT_WIDE)
+      xpass_hinge<T, A1, MODE, true, 64>(a, b, local);
+  } else if ((FS & FT_GEN) && b.mode == BM_GEN_SLOT) {
+    xpass_slot<T, A1, MODE>(a, b, local);
+  } else if ((FS & FT_GEN) && (b.kind == KD_NONOVERLAP || b.kind == KD_WALL)) {
+    xpass_geom<T, A1, MODE>(a, b, local);
+  } else if (FS & FT_WIDE) {
+    if (b.kind == KD_HINGE) {
+      if (b.dmax <= 32)
+        xpass_hinge<T, A1, MODE, false, 32>(a, b, local);
+      else
+        xpass_hinge<T, A1, MODE, false, 64>(a, b, local);
+    } else {
+      xpass_lindyn<T, A1, MODE>(a, b, local);
+    }
+  }
+}
+
+// z_b = sum(contributions) / deg(b).  Blocks [0, nb_w): four long lists
+// per block, one wavefront each (lanes stride the list, then a fixed
+// tree); remaining blocks: one short list per lane, summed in order.
+template <typename T>
+__global__ __launch_bounds__(NT) void zpass_kernel(ZArgs<T> a) {
+  T dmax = T(0);
+  if ((int)blockIdx.x < a.nb_w) {
+    const int lane = threadIdx.x & 63;
+    const int64_t k = (int64_t)blockIdx.x * (NT / 64) + (threadIdx.x >> 6);
+    const bool ok = k < a.n_w;
+    T s = T(0);
+    if (ok) {
+      const int64_t o1 = a.rng_w[2 * k + 1];
+      for (int64_t j = a.rng_w[2 * k] + lane; j < o1; j += 64) s += a.pool[a.csr[j]];
+    }
+    s = admmi::wave_sum(s);
+    if (ok && lane == 0) {
+      const int zi = a.var_w[k];
+      const T zn = s / a.deg_w[k];
+      a.zout[zi] = zn;
+      if (a.check) dmax = tabs(zn - a.zin[zi]);
+    }
+  } else {
+    const int64_t k = (int64_t)(blockIdx.x - a.nb_w) * NT + threadIdx.x;
+    if (k < a.n_l) {
+      const int zi = a.var_l[k];
+      const int64_t o0 = a.rng_l[2 * k], o1 = a.rng_l[2 * k + 1];
+      T zn = a.zin[zi];
+      if (o1 > o0) {
+        T s = T(0);
+        for (int64_t j = o0; j < o1; ++j) s += a.pool[a.csr[j]];
+        zn = s / a.deg_l[k];
+      }
+      a.zout[zi] = zn;
+      if (a.check) dmax = tabs(zn - a.zin[zi]);
+    }
+  }
+  if (a.check) block_max_store(dmax, a.blockmax);
+}
+
+// State import: m = u + z_b (x = z_b) for every user slot.
+template <typename T>
+__global__ void set_state_kernel(int64_t ns, const int64_t* upos, const int32_t* uz,
+                                 const double* u, const T* z, T* pool, int64_t xdelta,
+                                 int write_x) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ns) return;
+  const T zv = z[uz[i]];
+  const T uv = u ? (T)u[i] : T(0);
+  pool[upos[i]] = uv + zv;
+  if (write_x) pool[upos[i] + xdelta] = zv;
+}
+
+// Export of u (which = 0), x (which = 1) in user slot order.
+template <typename T, bool A1>
+__global__ void get_slots_kernel(int64_t ns, const int64_t* upos, const int32_t* uz,
+                                 const T* pool, const T* z, int64_t xdelta, T alpha,
+                                 int which, double* out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ns) return;
+  const int64_t p = upos[i];
+  const T zv = z[uz[i]];
+  if (which == 1) {
+    out[i] = (double)pool[p + xdelta];
+    return;
+  }
+  T u;
+  if constexpr (A1) {
+    u = pool[p] - zv;
+  } else {
+    const T xo = pool[p + xdelta];
+    u = (pool[p] - xo) + alpha * (xo - zv);
+  }
+  out[i] = (double)u;
+}
+
+template <typename T>
+__global__ void convert_kernel(int64_t n, const double* in, T* out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = (T)in[i];
+}
+
+template <typename T>
+__global__ void widen_kernel(int64_t n, const T* in, double* out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = (double)in[i];
+}
+
+}  // namespace admmg

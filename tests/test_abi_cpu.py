@@ -1,0 +1,131 @@
+"""C ABI checks that need no GPU: the library loads, exports every function
+declared in include/admm.h, validates graphs and reports layout sizes.
+No compute call is made here."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import workloads as W
+from paper_1603_02526_amd import admm as A
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = set()
+    inc = os.path.join(ROOT, "include")
+    for fn in os.listdir(inc):
+        if fn.endswith(".h"):
+            txt = open(os.path.join(inc, fn)).read()
+            txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+            names |= set(re.findall(r"\b(admm_[a-z0-9_]+)\s*\(", txt))
+    return sorted(names)
+
+
+def test_library_exports_every_declared_symbol():
+    L = A.lib()
+    names = _declared()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(L, n), n
+    assert L.admm_abi_version() == 1
+
+
+def _finalize_cpu(g):
+    """finalize on a machine without a GPU validates and reports NO_DEVICE."""
+    try:
+        g.finalize(0)
+        return A.OK
+    except A.AdmmError as e:
+        return e.status
+
+
+@pytest.mark.parametrize("name,tiles,buckets", [("packing_tri10", 1, 3),
+                                                ("packing_sq2000", 528, 3)])
+def test_packing_layout(name, tiles, buckets):
+    p = W.workload(name)
+    g = A.Graph.from_problem(p, device=None)
+    assert _finalize_cpu(g) in (A.OK, A.E_NO_DEVICE)
+    inf = g.info()
+    assert inf["n_edges"] == p.n_edges and inf["n_slots"] == p.n_slots
+    assert inf["n_factors"] == p.n_factors and inf["n_scalars"] == p.n_scalars
+    assert inf["n_pair_tiles"] == tiles and inf["n_buckets"] == buckets
+    # algorithmic bytes: m read + write per slot, plus wall/radius/pair data
+    assert inf["algo_bytes_per_iter"] >= 8 * p.n_slots
+
+
+def test_svm_layout():
+    p = W.svm(5000, 20, seed=3)
+    g = A.Graph.from_problem(p, device=None)
+    assert _finalize_cpu(g) in (A.OK, A.E_NO_DEVICE)
+    inf = g.info()
+    assert inf["n_edges"] == 5000 * 21 + 20
+    assert inf["n_pair_tiles"] == 0
+    # one partial per variable per 256-factor workgroup, plus 20 L2 slots
+    assert inf["n_contributions"] == 20 * 21 + 20
+
+
+def test_incomplete_pairs_fall_back_to_general_layout():
+    p = W.packing(12, "square", 0.05, seed=2)
+    g0 = p.groups[0]
+    p.groups[0] = W.FactorGroup("nonoverlap", g0.var_ids[:-1], g0.params, True)
+    g = A.Graph.from_problem(p, device=None)
+    assert _finalize_cpu(g) in (A.OK, A.E_NO_DEVICE)
+    assert g.info()["n_pair_tiles"] == 0
+
+
+def _expect(status, fn, *args):
+    with pytest.raises(A.AdmmError) as ei:
+        fn(*args)
+    assert ei.value.status == status, str(ei.value)
+
+
+def test_validation_errors():
+    g = A.Graph([2, 1, 2, 1])
+    _expect(A.E_ARG, g.add_factors, "nonoverlap", [[0, 1, 2, 7]])        # bad id
+    _expect(A.E_ARG, g.add_factors, "nonoverlap", [[0, 1, 2, 2]])        # repeated
+    _expect(A.E_ARG, g.add_factors, "wall", [[0, 1]], [[1.0, 0.0]])      # param_len
+    _expect(A.E_ARG, g.add_factors, "nonoverlap", [[0, 1, 3, 2]])        # wrong dims
+    g = A.Graph([2, 1])
+    g.add_factors("radius", [[1]], [1.0], shared=True)
+    _expect(A.E_NUMERIC, g.finalize, 0)                                   # rho <= gamma
+    g = A.Graph([1, 1, 1])
+    _expect(A.E_ARG, g.add_factors, "hinge", [[0, 1, 2]], [[1.0, 2.0, 1.0, -1.0]])  # C < 0
+    g = A.Graph([3])
+    _expect(A.E_ARG, g.add_factors, "quad", [[0]], [[1.0, 2.0]])          # weight short
+    g = A.Graph([3])
+    _expect(A.E_ARG, g.add_factors, "box", [[0]], [1.0, -1.0], True)     # lo > hi
+    _expect(A.E_ARG, A.Graph, [1, 0])                                      # dim 0
+    _expect(A.E_ARG, A.Graph, [1], 7)                                      # precision
+    g = A.Graph([1])
+    _expect(A.E_ARG, g.set_rho, -1.0)
+    _expect(A.E_ARG, g.set_alpha, 0.0)
+
+
+def test_state_machine():
+    g = A.Graph([1])
+    g.add_factors("l2", [[0]], [1.0], shared=True)
+    _expect(A.E_STATE, g.run, 1)
+    _expect(A.E_STATE, g.z)
+    st = _finalize_cpu(g)
+    if st == A.E_NO_DEVICE:
+        _expect(A.E_STATE, g.run, 1)
+        _expect(A.E_STATE, g.add_factors, "l2", [[0]], [1.0], True)
+        _expect(A.E_STATE, g.set_rho, 2.0)
+
+
+def test_lindyn_limits_and_shapes():
+    inst = W.mpc_batch(1, seed=9)[0]
+    p = W.mpc_graph(inst)
+    g = A.Graph.from_problem(p, device=None)
+    assert _finalize_cpu(g) in (A.OK, A.E_NO_DEVICE)
+    assert g.info()["n_slots"] == p.n_slots == inst.T * (3 * inst.n + 3 * inst.m) - inst.n
+    # n above the register-resident limit is refused, not silently slowed
+    rng = np.random.default_rng(0)
+    A_, B_ = W.mpc_system(rng, 20, 2)
+    big = W.MPCInstance(5, 20, 2, A_, B_, np.zeros(20), np.ones(20), np.ones(2), 1.0)
+    g = A.Graph.from_problem(W.mpc_graph(big), device=None)
+    _expect(A.E_UNSUPPORTED, g.finalize, 0)
