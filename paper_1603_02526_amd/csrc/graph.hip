@@ -25,6 +25,8 @@
 #include <numeric>
 #include <vector>
 
+#include <hip/hip_ext.h>
+
 #include "graph_kernels.h"
 
 using namespace admmg;
@@ -716,25 +718,28 @@ struct Engine : EngineBase {
     return a;
   }
 
+  // Launches take an optional start/stop event pair recorded at the
+  // kernel's own begin and end (hipExtLaunchKernelGGL), used for timing.
   template <bool A1, int FS>
-  void launch_x_fs(int mode, hipStream_t st) {
+  void launch_x_fs(int mode, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
     XArgs<T> a = xargs();
+    const dim3 g((unsigned)xblocks), b(NT);
     if (mode == PM_NORMAL)
-      xpass_kernel<T, A1, PM_NORMAL, FS><<<(unsigned)xblocks, NT, 0, st>>>(a);
+      hipExtLaunchKernelGGL((xpass_kernel<T, A1, PM_NORMAL, FS>), g, b, 0, st, e0, e1, 0, a);
     else if (mode == PM_SAVE)
-      xpass_kernel<T, A1, PM_SAVE, FS><<<(unsigned)xblocks, NT, 0, st>>>(a);
+      hipExtLaunchKernelGGL((xpass_kernel<T, A1, PM_SAVE, FS>), g, b, 0, st, e0, e1, 0, a);
     else
-      xpass_kernel<T, A1, PM_RESID, FS><<<(unsigned)xblocks, NT, 0, st>>>(a);
+      hipExtLaunchKernelGGL((xpass_kernel<T, A1, PM_RESID, FS>), g, b, 0, st, e0, e1, 0, a);
   }
 
   template <bool A1>
-  void launch_x(int mode, hipStream_t st) {
-    if (fs == FS_PAIR) launch_x_fs<A1, FS_PAIR>(mode, st);
-    else if (fs == FS_HINGE) launch_x_fs<A1, FS_HINGE>(mode, st);
-    else launch_x_fs<A1, FS_ALL>(mode, st);
+  void launch_x(int mode, hipStream_t st, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
+    if (fs == FS_PAIR) launch_x_fs<A1, FS_PAIR>(mode, st, e0, e1);
+    else if (fs == FS_HINGE) launch_x_fs<A1, FS_HINGE>(mode, st, e0, e1);
+    else launch_x_fs<A1, FS_ALL>(mode, st, e0, e1);
   }
 
-  void launch_z(int check, hipStream_t st) {
+  void launch_z(int check, hipStream_t st, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
     ZArgs<T> a;
     a.pool = pool;
     a.csr = csr;
@@ -751,7 +756,8 @@ struct Engine : EngineBase {
     a.zout = z[zc ^ 1];
     a.blockmax = bmz;
     a.check = check;
-    if (zblocks) zpass_kernel<T><<<(unsigned)zblocks, NT, 0, st>>>(a);
+    if (zblocks)
+      hipExtLaunchKernelGGL((zpass_kernel<T>), dim3((unsigned)zblocks), dim3(NT), 0, st, e0, e1, 0, a);
     zc ^= 1;
   }
 
@@ -787,15 +793,20 @@ struct Engine : EngineBase {
     admm_status rc = ADMM_OK;
     for (int32_t k = 0; k < iters; ++k) {
       const bool last = (k == iters - 1);
-      hipEventRecord(ev[4 * k + 0], st);
       if (xblocks) {
-        if (alpha1) launch_x<true>(last ? PM_SAVE : PM_NORMAL, st);
-        else launch_x<false>(PM_NORMAL, st);
+        if (alpha1) launch_x<true>(last ? PM_SAVE : PM_NORMAL, st, ev[4 * k + 0], ev[4 * k + 1]);
+        else launch_x<false>(PM_NORMAL, st, ev[4 * k + 0], ev[4 * k + 1]);
+      } else {
+        hipEventRecord(ev[4 * k + 0], st);
+        hipEventRecord(ev[4 * k + 1], st);
       }
-      hipEventRecord(ev[4 * k + 1], st);
-      hipEventRecord(ev[4 * k + 2], st);
-      launch_z(last ? 1 : 0, st);
-      hipEventRecord(ev[4 * k + 3], st);
+      if (zblocks) {
+        launch_z(last ? 1 : 0, st, ev[4 * k + 2], ev[4 * k + 3]);
+      } else {
+        hipEventRecord(ev[4 * k + 2], st);
+        launch_z(last ? 1 : 0, st);
+        hipEventRecord(ev[4 * k + 3], st);
+      }
     }
     if (xblocks) {
       if (alpha1) launch_x<true>(PM_RESID, st);
