@@ -167,6 +167,74 @@ admm_status admm_z_device_ptr(admm_graph* g, void** z_dev);
 
 admm_status admm_graph_destroy(admm_graph* g);
 
+/* ------------------------------------------------------------------------
+ * Batched linear MPC (paper Sec. V-B; App. B proximal operators).
+ * Instance i: x_{t+1} = A_i x_t + B_i u_t, t = 0..T_i-1, x_0 given per solve;
+ * cost 1/2 sum_{t=1..T} x_t^T diag(q_i) x_t + 1/2 sum_{t=0..T-1} u_t^T
+ * diag(r_i) u_t; |u_t|_inf <= u_box_i when u_box_i > 0.  Its factor graph
+ * has variable nodes u_t (dim m) and x_{t+1} (dim n) and, per step, a
+ * linear-dynamics factor, a quadratic factor on u_t and on x_{t+1} and a box
+ * factor on u_t; alpha = 1.  Limits: T <= 256, n <= 12, m <= 4.
+ * z layout of instance i (offset zoff_i = sum_{j<i} T_j (n_j + m_j)): per
+ * step t the m entries of u_t then the n entries of x_{t+1}.
+ * Per-edge dual layout (offset sum_{j<i} 3 T_j (n_j + m_j)): per step t
+ * [dyn x_t (n) | dyn u_t (m) | dyn x_{t+1} (n) | quad u_t (m) | box u_t (m) |
+ * quad x_{t+1} (n)]; the x_t entries of step 0 are unused.
+ * ------------------------------------------------------------------------ */
+typedef struct admm_mpc_batch admm_mpc_batch;
+
+/* Host arrays (copied): T, n, m [n_inst]; A (n_i*n_i), B (n_i*m_i), q (n_i),
+ * r (m_i) concatenated over instances, row-major; u_box [n_inst].  rho > 0.
+ * Precomputes the projection matrices and uploads everything to `device`.
+ * ADMM_E_UNSUPPORTED beyond the limits above (checked before any device
+ * call). */
+admm_status admm_mpc_batch_create(int32_t n_inst, const int32_t* T, const int32_t* n,
+                                  const int32_t* m, const double* A, const double* B,
+                                  const double* q, const double* r, const double* u_box,
+                                  double rho, int32_t device, admm_mpc_batch** out);
+
+/* Element counts of the batch's z, per-edge dual and x0 arrays. */
+admm_status admm_mpc_batch_sizes(const admm_mpc_batch* b, int64_t* z_total,
+                                 int64_t* u_total, int64_t* x0_total);
+
+/* Solve every instance in one persistent launch, asynchronously on `stream`.
+ * Device arrays (float32 / int32): x0 [x0_total]; z_init [z_total] or NULL
+ * (cold start, z = 0); z_out [z_total]; iters_out [n_inst].  dual_mode 0:
+ * u^0 = 0; 1: u^0 from dual completion of z_init (requires z_init).  Each
+ * instance stops at the first iteration with r = max_e |x_e - z_b| <= tol and
+ * s = rho max_b |z_b - z_b(previous)| <= tol; iters_out holds that iteration,
+ * or -max_iter when it did not converge. */
+admm_status admm_mpc_batch_solve(admm_mpc_batch* b, const float* x0, const float* z_init,
+                                 int32_t dual_mode, float tol, int32_t max_iter,
+                                 float* z_out, int32_t* iters_out, void* stream);
+
+/* Dual completion only (device arrays): u [u_total] from z [z_total].  At a
+ * solution z* it gives the duals that make (z*, u) a fixed point. */
+admm_status admm_mpc_batch_dual_complete(admm_mpc_batch* b, const float* z, float* u,
+                                         void* stream);
+
+/* Schedule of the persistent launch: pack1 = instances per workgroup for
+ * T <= 64 (1, 2 or 4), order (0 as given, 1 most work first, 2 grouped by
+ * (n, m)), grid = workgroups (0: as many as fit on the device at once).
+ * Results do not depend on the plan (bitwise). */
+admm_status admm_mpc_batch_set_plan(admm_mpc_batch* b, int32_t pack1, int32_t order,
+                                    int32_t grid);
+admm_status admm_mpc_batch_get_plan(const admm_mpc_batch* b, int32_t* pack1,
+                                    int32_t* order, int32_t* grid, int32_t* resident);
+
+/* Autotuner: time every candidate plan on cold solves of this batch from x0
+ * (device), reps launches each (best time kept), then keep the fastest.
+ * z_scratch [z_total] and iters_scratch [n_inst] are device work arrays;
+ * times_ms [max_candidates] (host, nullable) receives each candidate's time.
+ * Synchronises the stream. */
+admm_status admm_mpc_batch_tune(admm_mpc_batch* b, const float* x0, float tol,
+                                int32_t max_iter, float* z_scratch,
+                                int32_t* iters_scratch, int32_t reps, float* times_ms,
+                                int32_t max_candidates, int32_t* n_candidates,
+                                void* stream);
+
+admm_status admm_mpc_batch_destroy(admm_mpc_batch* b);
+
 #ifdef __cplusplus
 }
 #endif

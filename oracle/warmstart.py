@@ -1,0 +1,98 @@
+"""Oracle of the MPC warm start (test infrastructure only, FP64 numpy).
+
+Dual completion: given a predicted trajectory z (per step (u_t, x_{t+1})),
+choose the initial duals u^0 of every edge so that (z, u^0) would be a fixed
+point of Algorithm 2 if z were optimal.  At a fixed point x = z for every
+factor, so -rho u_a is a subgradient of f_a at z, and the duals around each
+variable sum to zero (the z- and u-updates keep that sum at zero from
+u^0 = 0).  For the MPC graph this fixes every dual by one backward pass over
+the dynamics multipliers mu_t:
+    mu_{T-1} = Q x_T,   mu_{t-1} = A^T mu_t + Q x_t
+    rho u[dyn_t]  = (-A^T mu_t, -B^T mu_t, mu_t)  on (x_t, u_t, x_{t+1})
+                    (t = 0: (-B^T mu_0, mu_0) on (u_0, x_1))
+    rho u[quad x_t] = -Q x_t,   rho u[quad u_t] = -R u_t
+    rho u[box u_t]  = B^T mu_t + R u_t
+The returned vector follows the edge order of ``workloads.mpc_graph``.
+
+Also a plain FP64 MLP (forward, mean-squared-error backward, Adam step) that
+the GPU training kernels are checked against.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def dual_completion(inst, z, rho: float = 1.0) -> np.ndarray:
+    T, n, m = inst.T, inst.n, inst.m
+    blk = np.asarray(z, dtype=np.float64).reshape(T, n + m)
+    U = blk[:, :m]                  # u_0..u_{T-1}
+    X = blk[:, m:]                  # x_1..x_T
+    Q, R = np.diag(inst.q), np.diag(inst.r)
+    A, B = inst.A, inst.B
+    mu = np.zeros((T, n))
+    mu[T - 1] = Q @ X[T - 1]
+    for t in range(T - 1, 0, -1):
+        mu[t - 1] = A.T @ mu[t] + Q @ X[t - 1]
+    out = []
+    # dyn_0 on (u_0, x_1)
+    out.append(-(B.T @ mu[0]) / rho)
+    out.append(mu[0] / rho)
+    # dyn_t on (x_t, u_t, x_{t+1}), t = 1..T-1
+    for t in range(1, T):
+        out.append(-(A.T @ mu[t]) / rho)
+        out.append(-(B.T @ mu[t]) / rho)
+        out.append(mu[t] / rho)
+    # quadratic on x_1..x_T, then on u_0..u_{T-1}
+    for t in range(T):
+        out.append(-(Q @ X[t]) / rho)
+    for t in range(T):
+        out.append(-(R @ U[t]) / rho)
+    if inst.u_box > 0:
+        for t in range(T):
+            out.append((B.T @ mu[t] + R @ U[t]) / rho)
+    return np.concatenate(out)
+
+
+# ---------------------------------------------------------------------------
+# Plain MLP: y = W3 relu(W2 relu(W1 x + b1) + b2) + b3, loss = mean((y - t)^2)
+# ---------------------------------------------------------------------------
+
+def mlp_forward(params, x):
+    W1, b1, W2, b2, W3, b3 = params
+    h1p = x @ W1.T + b1
+    h1 = np.maximum(h1p, 0.0)
+    h2p = h1 @ W2.T + b2
+    h2 = np.maximum(h2p, 0.0)
+    y = h2 @ W3.T + b3
+    return y, (x, h1p, h1, h2p, h2)
+
+
+def mlp_loss_grad(params, x, target):
+    """Mean over all batch*outputs entries of (y - target)^2 and its gradient."""
+    W1, b1, W2, b2, W3, b3 = params
+    y, (x, h1p, h1, h2p, h2) = mlp_forward(params, x)
+    N = y.size
+    diff = y - target
+    loss = float(np.sum(diff * diff) / N)
+    gy = 2.0 * diff / N
+    gW3 = gy.T @ h2
+    gb3 = gy.sum(0)
+    gh2 = gy @ W3 * (h2p > 0)
+    gW2 = gh2.T @ h1
+    gb2 = gh2.sum(0)
+    gh1 = gh2 @ W2 * (h1p > 0)
+    gW1 = gh1.T @ x
+    gb1 = gh1.sum(0)
+    return loss, [gW1, gb1, gW2, gb2, gW3, gb3]
+
+
+def adam_step(params, grads, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One Adam update (Kingma & Ba) in place; step counts from 1."""
+    for p, g, mm, vv in zip(params, grads, m, v):
+        mm *= beta1
+        mm += (1 - beta1) * g
+        vv *= beta2
+        vv += (1 - beta2) * g * g
+        mhat = mm / (1 - beta1 ** step)
+        vhat = vv / (1 - beta2 ** step)
+        p -= lr * mhat / (np.sqrt(vhat) + eps)

@@ -129,3 +129,21 @@ def test_lindyn_limits_and_shapes():
     big = W.MPCInstance(5, 20, 2, A_, B_, np.zeros(20), np.ones(20), np.ones(2), 1.0)
     g = A.Graph.from_problem(W.mpc_graph(big), device=None)
     _expect(A.E_UNSUPPORTED, g.finalize, 0)
+
+
+def test_mpc_batch_validation_before_device():
+    from paper_1603_02526_amd import mpc as M
+    rng = np.random.default_rng(1)
+    A_, B_ = W.mpc_system(rng, 13, 2)
+    bad = W.MPCInstance(10, 13, 2, A_, B_, np.zeros(13), np.ones(13), np.ones(2), 1.0)
+    _expect(A.E_UNSUPPORTED, M.MPCBatch, [bad])
+    A_, B_ = W.mpc_system(rng, 4, 5)
+    bad = W.MPCInstance(10, 4, 5, A_, B_, np.zeros(4), np.ones(4), np.ones(5), 1.0)
+    _expect(A.E_UNSUPPORTED, M.MPCBatch, [bad])
+    A_, B_ = W.mpc_system(rng, 4, 2)
+    bad = W.MPCInstance(257, 4, 2, A_, B_, np.zeros(4), np.ones(4), np.ones(2), 1.0)
+    _expect(A.E_UNSUPPORTED, M.MPCBatch, [bad])
+    neg = W.MPCInstance(10, 4, 2, A_, B_, np.zeros(4), -np.ones(4), np.ones(2), 1.0)
+    _expect(A.E_ARG, M.MPCBatch, [neg])
+    ok = W.MPCInstance(10, 4, 2, A_, B_, np.zeros(4), np.ones(4), np.ones(2), 1.0)
+    _expect(A.E_ARG, M.MPCBatch, [ok], -1.0)

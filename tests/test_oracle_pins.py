@@ -142,3 +142,48 @@ def test_fig1_edge_order():
     g = O.OracleGraph(p)
     np.testing.assert_array_equal(g.slot_z, [0, 1, 2, 0, 3, 4, 1, 4, 4])
     assert g.n_z == 5
+
+
+@pytest.mark.parametrize("seed", [51, 52, 53])
+def test_dual_completion_is_the_converged_dual(seed):
+    """At the solution z*, the completed duals equal the duals ADMM itself
+    converges to, sum to zero around every variable, and make (z*, u0) a
+    fixed point: the next iteration already meets the 1e-4 stopping rule."""
+    from oracle import warmstart as WS
+    inst = W.mpc_batch(1, seed=seed, T_range=(15, 30))[0]
+    p = W.mpc_graph(inst)
+    g = O.OracleGraph(p)
+    g.run(200000, tol=1e-13)
+    zs, us = g.z, g.u
+    u0 = WS.dual_completion(inst, zs)
+    assert u0.shape == us.shape
+    np.testing.assert_allclose(u0, us, atol=1e-9)
+    sz = g.slot_z
+    np.testing.assert_allclose(np.bincount(sz, weights=u0, minlength=g.n_z), 0.0, atol=1e-12)
+    h = O.OracleGraph(p)
+    h.set_state(zs, u0)
+    assert h.run(10000, tol=1e-4) == 1
+    # completed duals of an arbitrary trajectory still sum to zero per variable
+    zr = np.random.default_rng(seed).standard_normal(zs.shape)
+    np.testing.assert_allclose(np.bincount(sz, weights=WS.dual_completion(inst, zr),
+                                           minlength=g.n_z), 0.0, atol=1e-10)
+
+
+def test_mlp_oracle_gradient_matches_finite_differences():
+    from oracle import warmstart as WS
+    rng = np.random.default_rng(3)
+    shapes = [(5, 4), (5,), (6, 5), (6,), (3, 6), (3,)]
+    params = [rng.standard_normal(s) * 0.5 for s in shapes]
+    x = rng.standard_normal((7, 4))
+    t = rng.standard_normal((7, 3))
+    loss, grads = WS.mlp_loss_grad(params, x, t)
+    h = 1e-6
+    for p, gp in zip(params, grads):
+        for idx in list(np.ndindex(p.shape))[:6]:
+            old = p[idx]
+            p[idx] = old + h
+            lp, _ = WS.mlp_loss_grad(params, x, t)
+            p[idx] = old - h
+            lm, _ = WS.mlp_loss_grad(params, x, t)
+            p[idx] = old
+            assert abs((lp - lm) / (2 * h) - gp[idx]) < 1e-6
