@@ -76,6 +76,84 @@ def cpu_baseline(problem, iters):
     return problem.n_edges * iters / dt, dt
 
 
+def _iter_stats(it):
+    import numpy as np
+    it = np.asarray(it)
+    ok = it > 0
+    v = it[ok]
+    return dict(mean=float(v.mean()) if v.size else None,
+                median=float(np.median(v)) if v.size else None,
+                p95=float(np.percentile(v, 95)) if v.size else None,
+                unconverged=int((~ok).sum()))
+
+
+def bench_mpc_batch(torch):
+    """4096 uneven instances (T 20..200, n 4..12, m 2..4), cold start, to
+    residual 1e-4, one persistent launch with the autotuned schedule."""
+    import numpy as np
+    import workloads as W
+    from paper_1603_02526_amd import mpc as M
+    insts = W.mpc_batch(4096, seed=1003)
+    b = M.MPCBatch(insts)
+    x0 = torch.tensor(b.pack_x0([i.x0 for i in insts]), device="cuda")
+    z = torch.zeros(b.z_total, device="cuda")
+    it = torch.zeros(b.n_inst, dtype=torch.int32, device="cuda")
+    cand = b.tune(x0, z, it, tol=1e-4, reps=2)
+    b.solve(x0, z, it, tol=1e-4)
+    torch.cuda.synchronize()
+    best = 1e30
+    for _ in range(5):
+        t0 = time.perf_counter()
+        b.solve(x0, z, it, tol=1e-4)
+        torch.cuda.synchronize()
+        best = min(best, time.perf_counter() - t0)
+    its = it.cpu().numpy()
+    return dict(instances=4096, seconds_per_batch=best, solves_per_s=4096 / best,
+                iterations=_iter_stats(its), plan=b.plan(),
+                tuner_candidates_ms=[round(c, 3) for c in cand],
+                instance_iterations_per_s=float(np.abs(its).sum()) / best)
+
+
+def bench_warmstart(torch, args):
+    """Warm-start family: systems n=8, m=3, T=100 (seed 2000+s); per system an
+    MLP 8 -> 256 -> 256 -> 1100 trained on GPU-solved x0 ~ N(0, I) (seed
+    3000+s), evaluated on 2048 fresh x0 (seed 4000+s) against cold start."""
+    import numpy as np
+    import workloads as W
+    from paper_1603_02526_amd import warmstart as WSm
+    systems = W.mpc_family(args.ws_systems, 8, 3, 100, 2000)
+    tot = {"cold": 0.0, "warm_z": 0.0, "warm": 0.0}
+    its = {"cold": [], "warm_z": [], "warm": []}
+    gen_s = train_s = 0.0
+    losses = []
+    for s, (A, B) in enumerate(systems):
+        sysd = WSm.System(A, B, 100, np.ones(8), np.full(3, 0.1), 1.0)
+        ws = WSm.WarmStart(sysd, batch=2048, hidden=256, init_seed=5000 + s)
+        t0 = time.perf_counter()
+        X, Z = ws.generate(args.ws_samples, seed=3000 + s)
+        gen_s += time.perf_counter() - t0
+        t0 = time.perf_counter()
+        hist = ws.train(X, Z, epochs=args.ws_epochs, lr=1e-3, lr_final=5e-5)
+        train_s += time.perf_counter() - t0
+        losses.append(hist[-1])
+        del X, Z
+        x0 = torch.tensor(W.mpc_x0(8, 2048, seed=4000 + s).astype(np.float32), device="cuda")
+        for mode in ("cold", "warm_z", "warm"):
+            dt, it = ws.timed(x0, mode)
+            tot[mode] += dt
+            its[mode].append(it)
+    n = 2048 * len(systems)
+    res = {mode: dict(solves_per_s=n / tot[mode], seconds=tot[mode],
+                      iterations=_iter_stats(np.concatenate(its[mode])))
+           for mode in tot}
+    res.update(systems=len(systems), eval_instances=n,
+               train_samples_per_system=args.ws_samples, epochs=args.ws_epochs,
+               final_train_mse=[round(l, 6) for l in losses],
+               data_generation_s=gen_s, training_s=train_s,
+               warm_over_cold=res["warm"]["solves_per_s"] / res["cold"]["solves_per_s"])
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -88,6 +166,11 @@ def main():
                     help="also run a plain 512 MiB device copy (for counter scaling)")
     ap.add_argument("--cpu-iters", type=int, default=100,
                     help="oracle iterations in the CPU-baseline sample")
+    ap.add_argument("--no-mpc", action="store_true", help="skip the batched MPC workloads")
+    ap.add_argument("--ws-samples", type=int, default=1_000_000,
+                    help="ADMM solutions per system for training the warm-start network")
+    ap.add_argument("--ws-epochs", type=int, default=6)
+    ap.add_argument("--ws-systems", type=int, default=8)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not "
@@ -161,6 +244,10 @@ def main():
                                     xpass_avg_us=x2 * 1e3 / 500,
                                     xpass_GBs=inf2["algo_bytes_per_iter"] / (x2 * 1e-3 / 500) / 1e9)
         out["secondary"] = secd
+
+    if not args.no_mpc:
+        out.setdefault("secondary", {})["mpc_batch_4096"] = bench_mpc_batch(torch)
+        out["secondary"]["mpc_warmstart"] = bench_warmstart(torch, args)
 
     if not args.no_cpu:
         cb_iters = args.cpu_iters

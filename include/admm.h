@@ -235,6 +235,39 @@ admm_status admm_mpc_batch_tune(admm_mpc_batch* b, const float* x0, float tol,
 
 admm_status admm_mpc_batch_destroy(admm_mpc_batch* b);
 
+/* ------------------------------------------------------------------------
+ * Learned warm start: an MLP x0 -> z0 (initial trajectory of an MPC
+ * instance), y = W3 relu(W2 relu(W1 x + b1) + b2) + b3, trained on the GPU
+ * with mean-squared error and Adam.  Every product runs on the matrix cores
+ * with bf16 operands (round to nearest even) and fp32 accumulation; master
+ * weights, activations and gradients are fp32.  Parameter vector order:
+ * W1 [hidden][n_in], b1 [hidden], W2 [hidden][hidden], b2 [hidden],
+ * W3 [n_out][hidden], b3 [n_out] (row-major).  The caller supplies the
+ * initial weights; nothing here draws random numbers.
+ * ------------------------------------------------------------------------ */
+typedef struct admm_mlp admm_mlp;
+
+/* Allocate parameters, Adam moments and activations for batches up to
+ * max_batch on `device`; parameters start at zero. */
+admm_status admm_mlp_create(int32_t n_in, int32_t hidden, int32_t n_out, int32_t max_batch,
+                            int32_t device, admm_mlp** out);
+/* Number of parameters (-1 for NULL). */
+int64_t admm_mlp_n_params(const admm_mlp* n);
+/* Host float arrays [n_params]; set also resets the Adam state. */
+admm_status admm_mlp_set_params(admm_mlp* n, const float* host);
+admm_status admm_mlp_get_params(admm_mlp* n, float* host);
+/* y [batch][n_out] = MLP(x [batch][n_in]); device arrays, async. */
+admm_status admm_mlp_forward(admm_mlp* n, const float* x, int32_t batch, float* y, void* stream);
+/* Gradient of mean((y - target)^2) over all batch*n_out entries: grads
+ * [n_params] (device, nullable) and loss (device scalar, nullable). */
+admm_status admm_mlp_grads(admm_mlp* n, const float* x, const float* target, int32_t batch,
+                           float* grads, float* loss, void* stream);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) on that
+ * loss; loss (device scalar, nullable) is the loss before the step. */
+admm_status admm_mlp_train_step(admm_mlp* n, const float* x, const float* target, int32_t batch,
+                                float lr, float* loss, void* stream);
+admm_status admm_mlp_destroy(admm_mlp* n);
+
 #ifdef __cplusplus
 }
 #endif

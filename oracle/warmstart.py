@@ -55,33 +55,51 @@ def dual_completion(inst, z, rho: float = 1.0) -> np.ndarray:
 
 # ---------------------------------------------------------------------------
 # Plain MLP: y = W3 relu(W2 relu(W1 x + b1) + b2) + b3, loss = mean((y - t)^2)
+# With bf16=True every matrix product takes its two operands rounded to
+# bf16 (round to nearest even from float32), as the GPU's matrix cores do;
+# the products themselves are exact FP64 sums.
 # ---------------------------------------------------------------------------
 
-def mlp_forward(params, x):
+def bf16_round(a):
+    """Round to bf16 (nearest even), via float32, returned as float64."""
+    f = np.asarray(a, dtype=np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    r = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    out = (r & 0xFFFFFFFF).astype(np.uint32).view(np.float32)
+    return out.astype(np.float64)
+
+
+def _mm(a, b, bf16):
+    if bf16:
+        return bf16_round(a) @ bf16_round(b)
+    return a @ b
+
+
+def mlp_forward(params, x, bf16=False):
     W1, b1, W2, b2, W3, b3 = params
-    h1p = x @ W1.T + b1
+    h1p = _mm(x, W1.T, bf16) + b1
     h1 = np.maximum(h1p, 0.0)
-    h2p = h1 @ W2.T + b2
+    h2p = _mm(h1, W2.T, bf16) + b2
     h2 = np.maximum(h2p, 0.0)
-    y = h2 @ W3.T + b3
+    y = _mm(h2, W3.T, bf16) + b3
     return y, (x, h1p, h1, h2p, h2)
 
 
-def mlp_loss_grad(params, x, target):
+def mlp_loss_grad(params, x, target, bf16=False):
     """Mean over all batch*outputs entries of (y - target)^2 and its gradient."""
     W1, b1, W2, b2, W3, b3 = params
-    y, (x, h1p, h1, h2p, h2) = mlp_forward(params, x)
+    y, (x, h1p, h1, h2p, h2) = mlp_forward(params, x, bf16)
     N = y.size
     diff = y - target
     loss = float(np.sum(diff * diff) / N)
     gy = 2.0 * diff / N
-    gW3 = gy.T @ h2
+    gW3 = _mm(gy.T, h2, bf16)
     gb3 = gy.sum(0)
-    gh2 = gy @ W3 * (h2p > 0)
-    gW2 = gh2.T @ h1
+    gh2 = _mm(gy, W3, bf16) * (h2 > 0)
+    gW2 = _mm(gh2.T, h1, bf16)
     gb2 = gh2.sum(0)
-    gh1 = gh2 @ W2 * (h1p > 0)
-    gW1 = gh1.T @ x
+    gh1 = _mm(gh2, W2, bf16) * (h1 > 0)
+    gW1 = _mm(gh1.T, x, bf16)
     gb1 = gh1.sum(0)
     return loss, [gW1, gb1, gW2, gb2, gW3, gb3]
 
@@ -96,3 +114,20 @@ def adam_step(params, grads, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):
         mhat = mm / (1 - beta1 ** step)
         vhat = vv / (1 - beta2 ** step)
         p -= lr * mhat / (np.sqrt(vhat) + eps)
+
+
+def mlp_shapes(n_in, hidden, n_out):
+    return [(hidden, n_in), (hidden,), (hidden, hidden), (hidden,), (n_out, hidden), (n_out,)]
+
+
+def unflatten(flat, n_in, hidden, n_out):
+    out, o = [], 0
+    for s in mlp_shapes(n_in, hidden, n_out):
+        k = int(np.prod(s))
+        out.append(np.asarray(flat[o:o + k], dtype=np.float64).reshape(s))
+        o += k
+    return out
+
+
+def flatten(params):
+    return np.concatenate([np.asarray(p).ravel() for p in params])

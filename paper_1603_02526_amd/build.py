@@ -17,7 +17,7 @@ CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libadmm_hip.so")
 OBJDIR = os.path.join(ROOT, "_build")
 
-SOURCES = ["api.hip", "graph.hip", "mpc.hip"]
+SOURCES = ["api.hip", "graph.hip", "mpc.hip", "mlp.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -1,0 +1,356 @@
+// Small MLP for the learned MPC warm start: y = W3 relu(W2 relu(W1 x + b1) +
+// b2) + b3, mean-squared-error loss, Adam.  Every matrix product runs on the
+// gfx950 matrix cores (v_mfma_f32_16x16x16bf16_1k): operands rounded to
+// bf16 (round to nearest even) while staged through LDS, products
+// accumulated in fp32.  Master weights, activations and gradients are fp32
+// in device memory.  Bias, ReLU and the ReLU mask of the backward pass are
+// fused into the product epilogues; reductions (loss, bias gradients) use a
+// fixed order, so results are deterministic.
+#include <hip/hip_ext.h>
+
+#include <algorithm>
+#include <cmath>
+#include <memory>
+#include <vector>
+
+#include "internal.h"
+
+namespace {
+
+typedef short v4s __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+constexpr int GT = 256;  // threads per GEMM workgroup (4 wavefronts)
+constexpr int BM = 64, BN = 64, BK = 16;
+
+__device__ __forceinline__ unsigned short f2bf(float f) {
+  unsigned int u = __float_as_uint(f);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (unsigned short)((u >> 16) | ((u & 0xffff) ? 0x40 : 0));
+  u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest even
+  return (unsigned short)(u >> 16);
+}
+
+enum Epi : int { EPI_PLAIN = 0, EPI_BIAS = 1, EPI_BIAS_RELU = 2, EPI_MASK = 3 };
+
+// C[M x N] = sum_k A(m,k) B(k,n); A(m,k) = TA ? A[k*lda+m] : A[m*lda+k],
+// B(k,n) = TB ? B[n*ldb+k] : B[k*ldb+n].  Epilogue per EPI.
+// Workgroup tile 64 x 64, each wavefront a 32 x 32 quarter as 2 x 2 MFMA
+// tiles of 16 x 16, K consumed 16 at a time through LDS.
+template <bool TA, bool TB, int EPI>
+__global__ __launch_bounds__(GT) void gemm_kernel(int M, int N, int K, const float* __restrict__ A,
+                                                 int lda, const float* __restrict__ B, int ldb,
+                                                 float* __restrict__ C, int ldc,
+                                                 const float* __restrict__ bias,
+                                                 const float* __restrict__ mask, int ldm) {
+  __shared__ unsigned short As[BM][BK + 4];
+  __shared__ unsigned short Bs[BK][BN + 4];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
+  v4f acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+  for (int k0 = 0; k0 < K; k0 += BK) {
+    // A tile 64 x 16: 1024 elements, 4 per thread
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = t + q * GT;
+      int r, c;
+      if (TA) { c = e / BM; r = e % BM; } else { r = e / BK; c = e % BK; }
+      const int gm = m0 + r, gk = k0 + c;
+      float v = 0.f;
+      if (gm < M && gk < K) v = TA ? A[(int64_t)gk * lda + gm] : A[(int64_t)gm * lda + gk];
+      As[r][c] = f2bf(v);
+    }
+    // B tile 16 x 64
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = t + q * GT;
+      int r, c;
+      if (TB) { c = e / BK; r = e % BK; } else { r = e / BN; c = e % BN; }
+      const int gk = k0 + r, gn = n0 + c;
+      float v = 0.f;
+      if (gk < K && gn < N) v = TB ? B[(int64_t)gn * ldb + gk] : B[(int64_t)gk * ldb + gn];
+      Bs[r][c] = f2bf(v);
+    }
+    __syncthreads();
+    const int kq = (lane >> 4) * 4;
+    v4s af[2], bf[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int row = wm + i * 16 + (lane & 15);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) af[i][j] = (short)As[row][kq + j];
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int col = wn + i * 16 + (lane & 15);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) bf[i][j] = (short)Bs[kq + j][col];
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[i], bf[j], acc[i][j], 0, 0, 0);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int col = n0 + wn + j * 16 + (lane & 15);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int row = m0 + wm + i * 16 + (lane >> 4) * 4 + q;
+        if (row < M && col < N) {
+          float v = acc[i][j][q];
+          if (EPI == EPI_BIAS || EPI == EPI_BIAS_RELU) v += bias[col];
+          if (EPI == EPI_BIAS_RELU) v = v > 0.f ? v : 0.f;
+          if (EPI == EPI_MASK) v = mask[(int64_t)row * ldm + col] > 0.f ? v : 0.f;
+          C[(int64_t)row * ldc + col] = v;
+        }
+      }
+    }
+}
+
+// dY = 2 (y - target) / (rows * cols); per-block partial sums of (y - t)^2.
+__global__ __launch_bounds__(256) void mse_grad_kernel(int64_t n, const float* y, const float* tg,
+                                                       float scale, float* dy, float* part) {
+  __shared__ float red[256];
+  float s = 0.f;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    const float d = y[i] - tg[i];
+    dy[i] = 2.f * d * scale;
+    s += d * d;
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void finish_loss_kernel(int nb, const float* part, float scale, float* loss) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    float s = 0.f;
+    for (int i = 0; i < nb; ++i) s += part[i];
+    *loss = s * scale;
+  }
+}
+
+// db[c] = sum_r dY[r][c], one thread per column, rows in order.
+__global__ void colsum_kernel(int rows, int cols, const float* dY, float* db) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= cols) return;
+  float s = 0.f;
+  for (int r = 0; r < rows; ++r) s += dY[(int64_t)r * cols + c];
+  db[c] = s;
+}
+
+// Adam (Kingma and Ba), bias-corrected, on the flat parameter vector.
+__global__ void adam_kernel(int64_t n, float* p, const float* g, float* m, float* v, float lr,
+                            float b1, float b2, float eps, float c1, float c2) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.f - b1) * gi;
+  const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+}  // namespace
+
+struct admm_mlp {
+  int device = 0;
+  int n_in = 0, hid = 0, n_out = 0, max_batch = 0;
+  int64_t n_params = 0;
+  int64_t oW1, ob1, oW2, ob2, oW3, ob3;
+  float *p = nullptr, *g = nullptr, *am = nullptr, *av = nullptr;
+  float *h1 = nullptr, *h2 = nullptr, *y = nullptr, *dy = nullptr, *dh1 = nullptr, *dh2 = nullptr;
+  float* part = nullptr;
+  int64_t step = 0;
+  std::vector<void*> allocs;
+  ~admm_mlp() {
+    if (!allocs.empty()) {
+      hipSetDevice(device);
+      for (void* q : allocs) hipFree(q);
+    }
+  }
+};
+
+namespace {
+
+constexpr int LOSS_BLOCKS = 256;
+
+admm_status mlp_alloc(admm_mlp* n, float** q, int64_t count) {
+  ADMM_HIP(hipMalloc((void**)q, (size_t)std::max<int64_t>(count, 1) * sizeof(float)));
+  n->allocs.push_back(*q);
+  return ADMM_OK;
+}
+
+template <bool TA, bool TB, int EPI>
+void gemm(int M, int N, int K, const float* A, int lda, const float* B, int ldb, float* C, int ldc,
+          const float* bias, const float* mask, int ldm, hipStream_t st) {
+  dim3 grid((N + BN - 1) / BN, (M + BM - 1) / BM);
+  gemm_kernel<TA, TB, EPI><<<grid, GT, 0, st>>>(M, N, K, A, lda, B, ldb, C, ldc, bias, mask, ldm);
+}
+
+// forward: h1 = relu(x W1^T + b1), h2 = relu(h1 W2^T + b2), y = h2 W3^T + b3
+void forward(admm_mlp* n, const float* x, int batch, float* y, hipStream_t st) {
+  gemm<false, true, EPI_BIAS_RELU>(batch, n->hid, n->n_in, x, n->n_in, n->p + n->oW1, n->n_in, n->h1,
+                                   n->hid, n->p + n->ob1, nullptr, 0, st);
+  gemm<false, true, EPI_BIAS_RELU>(batch, n->hid, n->hid, n->h1, n->hid, n->p + n->oW2, n->hid, n->h2,
+                                   n->hid, n->p + n->ob2, nullptr, 0, st);
+  gemm<false, true, EPI_BIAS>(batch, n->n_out, n->hid, n->h2, n->hid, n->p + n->oW3, n->hid, y,
+                              n->n_out, n->p + n->ob3, nullptr, 0, st);
+}
+
+// gradients of mean((y - t)^2) into n->g; loss (device scalar) when non-null
+void backward(admm_mlp* n, const float* x, const float* tg, int batch, float* loss, hipStream_t st) {
+  forward(n, x, batch, n->y, st);
+  const int64_t ny = (int64_t)batch * n->n_out;
+  const float scale = 1.f / (float)ny;
+  mse_grad_kernel<<<LOSS_BLOCKS, 256, 0, st>>>(ny, n->y, tg, scale, n->dy, n->part);
+  if (loss) finish_loss_kernel<<<1, 64, 0, st>>>(LOSS_BLOCKS, n->part, scale, loss);
+  float* g = n->g;
+  // layer 3
+  gemm<true, false, EPI_PLAIN>(n->n_out, n->hid, batch, n->dy, n->n_out, n->h2, n->hid, g + n->oW3,
+                               n->hid, nullptr, nullptr, 0, st);
+  colsum_kernel<<<(n->n_out + 255) / 256, 256, 0, st>>>(batch, n->n_out, n->dy, g + n->ob3);
+  gemm<false, false, EPI_MASK>(batch, n->hid, n->n_out, n->dy, n->n_out, n->p + n->oW3, n->hid,
+                               n->dh2, n->hid, nullptr, n->h2, n->hid, st);
+  // layer 2
+  gemm<true, false, EPI_PLAIN>(n->hid, n->hid, batch, n->dh2, n->hid, n->h1, n->hid, g + n->oW2,
+                               n->hid, nullptr, nullptr, 0, st);
+  colsum_kernel<<<(n->hid + 255) / 256, 256, 0, st>>>(batch, n->hid, n->dh2, g + n->ob2);
+  gemm<false, false, EPI_MASK>(batch, n->hid, n->hid, n->dh2, n->hid, n->p + n->oW2, n->hid,
+                               n->dh1, n->hid, nullptr, n->h1, n->hid, st);
+  // layer 1
+  gemm<true, false, EPI_PLAIN>(n->hid, n->n_in, batch, n->dh1, n->hid, x, n->n_in, g + n->oW1,
+                               n->n_in, nullptr, nullptr, 0, st);
+  colsum_kernel<<<(n->hid + 255) / 256, 256, 0, st>>>(batch, n->hid, n->dh1, g + n->ob1);
+}
+
+}  // namespace
+
+extern "C" {
+
+admm_status admm_mlp_create(int32_t n_in, int32_t hidden, int32_t n_out, int32_t max_batch,
+                            int32_t device, admm_mlp** out) {
+  admmi::clear_err();
+  if (!out) return admmi::set_err(ADMM_E_ARG, "out is NULL");
+  *out = nullptr;
+  if (n_in < 1 || hidden < 1 || n_out < 1 || max_batch < 1)
+    return admmi::set_err(ADMM_E_ARG, "sizes must be >= 1");
+  std::unique_ptr<admm_mlp> n(new admm_mlp());
+  n->device = device;
+  n->n_in = n_in;
+  n->hid = hidden;
+  n->n_out = n_out;
+  n->max_batch = max_batch;
+  n->oW1 = 0;
+  n->ob1 = n->oW1 + (int64_t)hidden * n_in;
+  n->oW2 = n->ob1 + hidden;
+  n->ob2 = n->oW2 + (int64_t)hidden * hidden;
+  n->oW3 = n->ob2 + hidden;
+  n->ob3 = n->oW3 + (int64_t)n_out * hidden;
+  n->n_params = n->ob3 + n_out;
+  if (admm_status s = admmi::probe_device(device)) return s;
+  ADMM_HIP(hipSetDevice(device));
+  admm_status s;
+  const int64_t B = max_batch;
+  if ((s = mlp_alloc(n.get(), &n->p, n->n_params))) return s;
+  if ((s = mlp_alloc(n.get(), &n->g, n->n_params))) return s;
+  if ((s = mlp_alloc(n.get(), &n->am, n->n_params))) return s;
+  if ((s = mlp_alloc(n.get(), &n->av, n->n_params))) return s;
+  if ((s = mlp_alloc(n.get(), &n->h1, B * hidden))) return s;
+  if ((s = mlp_alloc(n.get(), &n->h2, B * hidden))) return s;
+  if ((s = mlp_alloc(n.get(), &n->y, B * n_out))) return s;
+  if ((s = mlp_alloc(n.get(), &n->dy, B * n_out))) return s;
+  if ((s = mlp_alloc(n.get(), &n->dh1, B * hidden))) return s;
+  if ((s = mlp_alloc(n.get(), &n->dh2, B * hidden))) return s;
+  if ((s = mlp_alloc(n.get(), &n->part, LOSS_BLOCKS))) return s;
+  ADMM_HIP(hipMemset(n->p, 0, n->n_params * sizeof(float)));
+  ADMM_HIP(hipMemset(n->am, 0, n->n_params * sizeof(float)));
+  ADMM_HIP(hipMemset(n->av, 0, n->n_params * sizeof(float)));
+  *out = n.release();
+  return ADMM_OK;
+}
+
+int64_t admm_mlp_n_params(const admm_mlp* n) { return n ? n->n_params : -1; }
+
+admm_status admm_mlp_set_params(admm_mlp* n, const float* host) {
+  admmi::clear_err();
+  if (!n || !host) return admmi::set_err(ADMM_E_ARG, "NULL argument");
+  ADMM_HIP(hipSetDevice(n->device));
+  ADMM_HIP(hipMemcpy(n->p, host, n->n_params * sizeof(float), hipMemcpyHostToDevice));
+  ADMM_HIP(hipMemset(n->am, 0, n->n_params * sizeof(float)));
+  ADMM_HIP(hipMemset(n->av, 0, n->n_params * sizeof(float)));
+  n->step = 0;
+  return ADMM_OK;
+}
+
+admm_status admm_mlp_get_params(admm_mlp* n, float* host) {
+  admmi::clear_err();
+  if (!n || !host) return admmi::set_err(ADMM_E_ARG, "NULL argument");
+  ADMM_HIP(hipSetDevice(n->device));
+  ADMM_HIP(hipMemcpy(host, n->p, n->n_params * sizeof(float), hipMemcpyDeviceToHost));
+  return ADMM_OK;
+}
+
+admm_status admm_mlp_forward(admm_mlp* n, const float* x, int32_t batch, float* y, void* stream) {
+  admmi::clear_err();
+  if (!n || !x || !y) return admmi::set_err(ADMM_E_ARG, "NULL argument");
+  if (batch < 1 || batch > n->max_batch) return admmi::set_err(ADMM_E_ARG, "batch out of [1, max_batch]");
+  ADMM_HIP(hipSetDevice(n->device));
+  forward(n, x, batch, y, (hipStream_t)stream);
+  ADMM_HIP(hipGetLastError());
+  return ADMM_OK;
+}
+
+admm_status admm_mlp_grads(admm_mlp* n, const float* x, const float* target, int32_t batch,
+                           float* grads, float* loss, void* stream) {
+  admmi::clear_err();
+  if (!n || !x || !target) return admmi::set_err(ADMM_E_ARG, "NULL argument");
+  if (batch < 1 || batch > n->max_batch) return admmi::set_err(ADMM_E_ARG, "batch out of [1, max_batch]");
+  ADMM_HIP(hipSetDevice(n->device));
+  hipStream_t st = (hipStream_t)stream;
+  backward(n, x, target, batch, loss, st);
+  if (grads) ADMM_HIP(hipMemcpyAsync(grads, n->g, n->n_params * sizeof(float), hipMemcpyDeviceToDevice, st));
+  ADMM_HIP(hipGetLastError());
+  return ADMM_OK;
+}
+
+admm_status admm_mlp_train_step(admm_mlp* n, const float* x, const float* target, int32_t batch,
+                                float lr, float* loss, void* stream) {
+  admmi::clear_err();
+  if (!n || !x || !target) return admmi::set_err(ADMM_E_ARG, "NULL argument");
+  if (batch < 1 || batch > n->max_batch) return admmi::set_err(ADMM_E_ARG, "batch out of [1, max_batch]");
+  if (!(lr > 0.f)) return admmi::set_err(ADMM_E_ARG, "lr must be > 0");
+  ADMM_HIP(hipSetDevice(n->device));
+  hipStream_t st = (hipStream_t)stream;
+  backward(n, x, target, batch, loss, st);
+  n->step += 1;
+  const float b1 = 0.9f, b2 = 0.999f;
+  const float c1 = 1.f - (float)std::pow(0.9, (double)n->step);
+  const float c2 = 1.f - (float)std::pow(0.999, (double)n->step);
+  adam_kernel<<<(unsigned)((n->n_params + 255) / 256), 256, 0, st>>>(n->n_params, n->p, n->g, n->am,
+                                                                     n->av, lr, b1, b2, 1e-8f, c1, c2);
+  ADMM_HIP(hipGetLastError());
+  return ADMM_OK;
+}
+
+admm_status admm_mlp_destroy(admm_mlp* n) {
+  admmi::clear_err();
+  delete n;
+  return ADMM_OK;
+}
+
+}  // extern "C"

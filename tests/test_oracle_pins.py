@@ -187,3 +187,14 @@ def test_mlp_oracle_gradient_matches_finite_differences():
             lm, _ = WS.mlp_loss_grad(params, x, t)
             p[idx] = old
             assert abs((lp - lm) / (2 * h) - gp[idx]) < 1e-6
+
+
+def test_bf16_rounding_matches_torch():
+    """The oracle's bf16 rounding equals torch's float32 -> bfloat16 cast."""
+    import torch
+    from oracle import warmstart as WS
+    rng = np.random.default_rng(9)
+    x = np.concatenate([rng.standard_normal(10000) * 10.0 ** rng.integers(-20, 20, 10000),
+                        [0.0, -0.0, 1.0, 1.00390625, 1.0078125, 3.0e38]]).astype(np.float32)
+    ref = torch.tensor(x).to(torch.bfloat16).to(torch.float64).numpy()
+    np.testing.assert_array_equal(WS.bf16_round(x), ref)
