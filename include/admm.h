@@ -120,6 +120,14 @@ admm_status admm_graph_add_factors(admm_graph* g, int32_t kind,
 admm_status admm_graph_set_rho(admm_graph* g, double rho);
 admm_status admm_graph_set_alpha(admm_graph* g, double alpha);
 
+/* Layout options, set before finalize.
+ *  ADMM_OPT_PAIR_ROWS: disks per row of a dense pair tile (16, 32 or 64;
+ *  0 = default, 64).  Each tile holds rows x 64 pairs and
+ *  is one workgroup of the x-pass; results do not depend on the choice
+ *  beyond the order of the z-sums. */
+enum { ADMM_OPT_PAIR_ROWS = 1 };
+admm_status admm_graph_set_option(admm_graph* g, int32_t option, int64_t value);
+
 /* Validate, bucket factors by kind, build the device layout (edge-major
  * structure-of-arrays per bucket, dense pair tiles for complete pairwise
  * non-overlap buckets, per-variable contribution lists) and upload it to
@@ -256,9 +264,20 @@ int64_t admm_mlp_n_params(const admm_mlp* n);
 /* Host float arrays [n_params]; set also resets the Adam state. */
 admm_status admm_mlp_set_params(admm_mlp* n, const float* host);
 admm_status admm_mlp_get_params(admm_mlp* n, float* host);
-/* y [batch][n_out] = MLP(x [batch][n_in]); device arrays, async. */
+/* Fixed (not trained) output affine y = mean + sd * yhat, yhat = W3 h2 + b3.
+ * The training loss is taken on normalised outputs, mean((yhat - (target -
+ * mean) / sd)^2), so every output is learned to the same relative accuracy
+ * and the bf16 products work on unit-scale values.  Default mean 0, sd 1.
+ * fit: per-output mean and standard deviation (floored at sd_min) of a
+ * device array targets [rows][n_out], FP64 accumulation, async. */
+admm_status admm_mlp_fit_output_scaling(admm_mlp* n, const float* targets, int64_t rows,
+                                        float sd_min, void* stream);
+admm_status admm_mlp_set_output_scaling(admm_mlp* n, const float* mean, const float* sd);
+admm_status admm_mlp_get_output_scaling(admm_mlp* n, float* mean, float* sd);
+/* y [batch][n_out] = MLP(x [batch][n_in]) including the output affine;
+ * device arrays, async. */
 admm_status admm_mlp_forward(admm_mlp* n, const float* x, int32_t batch, float* y, void* stream);
-/* Gradient of mean((y - target)^2) over all batch*n_out entries: grads
+/* Gradient of the normalised loss over all batch*n_out entries: grads
  * [n_params] (device, nullable) and loss (device scalar, nullable). */
 admm_status admm_mlp_grads(admm_mlp* n, const float* x, const float* target, int32_t batch,
                            float* grads, float* loss, void* stream);

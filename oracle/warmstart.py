@@ -75,20 +75,27 @@ def _mm(a, b, bf16):
     return a @ b
 
 
-def mlp_forward(params, x, bf16=False):
+def mlp_forward(params, x, bf16=False, mean=None, sd=None):
+    """Raw output yhat; with mean/sd given, also the denormalised
+    y = mean + sd * yhat (returned as the first value)."""
     W1, b1, W2, b2, W3, b3 = params
     h1p = _mm(x, W1.T, bf16) + b1
     h1 = np.maximum(h1p, 0.0)
     h2p = _mm(h1, W2.T, bf16) + b2
     h2 = np.maximum(h2p, 0.0)
     y = _mm(h2, W3.T, bf16) + b3
+    if mean is not None:
+        y = mean + sd * y
     return y, (x, h1p, h1, h2p, h2)
 
 
-def mlp_loss_grad(params, x, target, bf16=False):
-    """Mean over all batch*outputs entries of (y - target)^2 and its gradient."""
+def mlp_loss_grad(params, x, target, bf16=False, mean=None, sd=None):
+    """Mean over all batch*outputs entries of (yhat - (target - mean)/sd)^2
+    (mean 0, sd 1 when not given) and its gradient."""
     W1, b1, W2, b2, W3, b3 = params
     y, (x, h1p, h1, h2p, h2) = mlp_forward(params, x, bf16)
+    if mean is not None:
+        target = (target - mean) / sd
     N = y.size
     diff = y - target
     loss = float(np.sum(diff * diff) / N)

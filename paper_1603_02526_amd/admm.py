@@ -23,6 +23,7 @@ STATUS_NAMES = {0: "OK", 1: "E_ARG", 2: "E_STATE", 3: "E_NUMERIC", 4: "E_HIP",
 KIND = dict(nonoverlap=1, wall=2, radius=3, quad=4, box=5, hinge=6, l2=7,
             lindyn=8, lindyn0=9)
 FP32, FP64 = 0, 1
+OPT_PAIR_ROWS = 1
 
 
 class AdmmError(RuntimeError):
@@ -75,6 +76,7 @@ def lib():
         _sig(L, "admm_graph_set_rho", st, [VP, ctypes.c_double])
         _sig(L, "admm_graph_set_alpha", st, [VP, ctypes.c_double])
         _sig(L, "admm_graph_finalize", st, [VP, ctypes.c_int32])
+        _sig(L, "admm_graph_set_option", st, [VP, ctypes.c_int32, ctypes.c_int64])
         _sig(L, "admm_graph_info_get", st, [VP, ctypes.POINTER(GraphInfo)])
         _sig(L, "admm_set_state", st, [VP, DP, DP, VP])
         _sig(L, "admm_run", st, [VP, ctypes.c_int32, VP])
@@ -150,6 +152,9 @@ class Graph:
     def set_alpha(self, alpha: float):
         check(lib().admm_graph_set_alpha(self._h, float(alpha)))
 
+    def set_option(self, option: int, value: int):
+        check(lib().admm_graph_set_option(self._h, int(option), int(value)))
+
     def finalize(self, device: int = 0):
         check(lib().admm_graph_finalize(self._h, int(device)))
 
@@ -204,7 +209,8 @@ class Graph:
 
     @classmethod
     def from_problem(cls, problem, precision: int = FP32, device: Optional[int] = 0,
-                     rho: Optional[float] = None, alpha: Optional[float] = None):
+                     rho: Optional[float] = None, alpha: Optional[float] = None,
+                     pair_rows: int = 0):
         """Build from an object with var_dims, groups (kind, var_ids, params,
         shared), rho, alpha and z0.  device=None skips finalize."""
         g = cls(problem.var_dims, precision)
@@ -212,6 +218,8 @@ class Graph:
             g.add_factors(grp.kind, grp.var_ids, grp.params, grp.shared)
         g.set_rho(problem.rho if rho is None else rho)
         g.set_alpha(problem.alpha if alpha is None else alpha)
+        if pair_rows:
+            g.set_option(OPT_PAIR_ROWS, pair_rows)
         if device is not None:
             g.finalize(device)
             g.set_state(problem.z0)

@@ -48,8 +48,7 @@ struct Plan {
   std::vector<BucketDesc> bt;
   std::vector<int32_t> idx;
   std::vector<double> par;
-  int64_t n_part = 0, n_m = 0;  // partial and m-region element counts
-  std::vector<uint32_t> csr;    // contribution pool positions
+  int64_t n_zc = 0, n_m = 0;    // contribution buffer and m-region element counts
   std::vector<int32_t> var_w, var_l;
   std::vector<int64_t> rng_w, rng_l;
   std::vector<double> deg_w, deg_l;
@@ -83,6 +82,7 @@ struct admm_graph {
   int64_t nz = 0;
   std::vector<Group> groups;
   double rho = 1.0, alpha = 1.0;
+  int32_t pair_rows = 0;  // rows per dense pair tile (0: chosen at finalize)
   int64_t n_factors = 0, n_edges = 0, n_slots = 0;
   int state = 0;  // 0 building, 1 validated (no device), 2 ready
   int device = -1;
@@ -235,8 +235,10 @@ bool hinge_uniform(const Group& gr) {
 // Build the device layout.  Validation errors return non-OK.
 admm_status build_plan(admm_graph& g, Plan& P) {
   P = Plan();
-  struct Emit { int64_t z; int64_t pos; };  // pos: m-region or partial index
-  std::vector<Emit> em_part, em_m;          // contributions, in emission order
+  // Every contribution to a z scalar, in emission order: z index and the
+  // index-buffer slot that will receive its position in the z-major buffer.
+  struct Emit { int64_t z; int64_t key; };
+  std::vector<Emit> em;
   std::vector<int64_t> deg(g.nz, 0);
   P.upos.assign(g.n_slots, 0);
   P.uz.assign(g.n_slots, 0);
@@ -274,13 +276,20 @@ admm_status build_plan(admm_graph& g, Plan& P) {
       // ---------------- dense pair tiles ----------------
       b.mode = BM_PAIR;
       b.E = (int32_t)ezc.size();
-      b.NB = (b.E + PB - 1) / PB;
+      int RB = g.pair_rows;
+      if (RB == 0) RB = 64;  // measured fastest at 2000 disks (64: 19.4 us, 32: 21.6, 16: 23.5)
+      const int CB = PB;
+      b.rb = RB;
+      const int NBR = (b.E + RB - 1) / RB, NBC = (b.E + CB - 1) / CB;
+      b.NB = NBC;
       b.nslot = 6;
       std::vector<int32_t> tI, tJ;
-      std::vector<int64_t> tid((size_t)b.NB * b.NB, -1);
-      for (int I = 0; I < b.NB; ++I)
-        for (int J = I; J < b.NB; ++J) {
-          tid[(size_t)I * b.NB + J] = (int64_t)tI.size();
+      std::vector<int64_t> tid((size_t)NBR * NBC, -1);
+      for (int I = 0; I < NBR; ++I)
+        for (int J = 0; J < NBC; ++J) {
+          const int maxej = std::min(b.E, (J + 1) * CB) - 1;
+          if (maxej <= I * RB) continue;  // no pair e_i < e_j in this tile
+          tid[(size_t)I * NBC + J] = (int64_t)tI.size();
           tI.push_back(I);
           tJ.push_back(J);
         }
@@ -289,55 +298,50 @@ admm_status build_plan(admm_graph& g, Plan& P) {
       P.n_pair_tiles += b.n;
       for (int64_t t = 0; t < b.n; ++t) { P.idx.push_back(tI[t]); P.idx.push_back(tJ[t]); }
       for (int e = 0; e < b.E; ++e) { P.idx.push_back(ezc[e]); P.idx.push_back(ezr[e]); }
-      const int64_t TS = 6 * PB * PB;
+      const int64_t TS = 6LL * RB * CB;
+      const int64_t PS = 3LL * (RB + CB);
       P.n_m += b.n * TS;
-      b.part_off = P.n_part;
-      P.n_part += b.n * 6 * PB;
+      b.dst_off = (int64_t)P.idx.size();
+      P.idx.resize(P.idx.size() + b.n * PS, -1);
       b.blk0 = (int32_t)blocks;
       blocks += b.n;
       b.blk1 = (int32_t)blocks;
       // contributions: per tile, rows then columns with at least one pair
       for (int64_t t = 0; t < b.n; ++t) {
         const int I = tI[t], J = tJ[t];
-        const int64_t pb = b.part_off + t * 6 * PB;
-        for (int li = 0; li < PB; ++li) {
-          const int ei = I * PB + li;
-          if (ei >= b.E) break;
-          int cnt = 0;
-          for (int lj = 0; lj < PB; ++lj) {
-            const int ej = J * PB + lj;
-            if (ej < b.E && (I != J || li < lj)) ++cnt;
-          }
-          if (!cnt) continue;
-          em_part.push_back({ezc[ei], pb + li * 3});
-          em_part.push_back({ezc[ei] + 1, pb + li * 3 + 1});
-          em_part.push_back({ezr[ei], pb + li * 3 + 2});
+        const int maxej = std::min(b.E, (J + 1) * CB) - 1;
+        const int64_t pb = b.dst_off + t * PS;
+        for (int li = 0; li < RB; ++li) {
+          const int ei = I * RB + li;
+          if (ei >= b.E || ei >= maxej) break;
+          em.push_back({ezc[ei], pb + li * 3});
+          em.push_back({ezc[ei] + 1, pb + li * 3 + 1});
+          em.push_back({ezr[ei], pb + li * 3 + 2});
         }
-        for (int lj = 0; lj < PB; ++lj) {
-          const int ej = J * PB + lj;
+        for (int lj = 0; lj < CB; ++lj) {
+          const int ej = J * CB + lj;
           if (ej >= b.E) break;
-          const bool any = (I != J) ? true : (lj > 0);
-          if (!any) continue;
-          em_part.push_back({ezc[ej], pb + 3 * PB + lj * 3});
-          em_part.push_back({ezc[ej] + 1, pb + 3 * PB + lj * 3 + 1});
-          em_part.push_back({ezr[ej], pb + 3 * PB + lj * 3 + 2});
+          if (ej <= I * RB) continue;
+          em.push_back({ezc[ej], pb + 3 * RB + lj * 3});
+          em.push_back({ezc[ej] + 1, pb + 3 * RB + lj * 3 + 1});
+          em.push_back({ezr[ej], pb + 3 * RB + lj * 3 + 2});
         }
       }
       for (int64_t f = 0; f < gr.n; ++f) {
         const int e1 = fe1[f], e2 = fe2[f];
-        const int I = e1 / PB, li = e1 % PB, J = e2 / PB, lj = e2 % PB;
-        const int64_t t = tid[(size_t)I * b.NB + J];
-        const int64_t base = b.m_off + t * TS + li * PB + lj;
+        const int I = e1 / RB, li = e1 % RB, J = e2 / CB, lj = e2 % CB;
+        const int64_t t = tid[(size_t)I * NBC + J];
+        const int64_t base = b.m_off + t * TS + (int64_t)li * CB + lj;
         const int64_t zs[6] = {ezc[e1], ezc[e1] + 1, ezr[e1], ezc[e2], ezc[e2] + 1, ezr[e2]};
         for (int s = 0; s < 6; ++s) {
-          P.upos[us] = base + (int64_t)s * PB * PB;
+          P.upos[us] = base + (int64_t)s * RB * CB;
           P.uz[us] = (int32_t)zs[s];
           deg[zs[s]]++;
           ++us;
         }
       }
       P.algo_elems += 2 * (int64_t)gr.n * 6;
-      P.layout_elems += b.n * 6 * PB;  // partial writes
+
     } else if (gr.kind == KD_HINGE && gr.arity - 1 <= 64 && hinge_uniform(gr)) {
       // ---------------- hinge, shared variable list ----------------
       b.mode = BM_UNIF_HINGE;
@@ -361,13 +365,13 @@ admm_status build_plan(admm_graph& g, Plan& P) {
       }
       P.n_m += (int64_t)gr.arity * b.nfp;
       const int64_t tiles = (gr.n + NT - 1) / NT;
-      b.part_off = P.n_part;
-      P.n_part += tiles * gr.arity;
+      b.dst_off = (int64_t)P.idx.size();
+      P.idx.resize(P.idx.size() + tiles * gr.arity, -1);
       b.blk0 = (int32_t)blocks;
       blocks += tiles;
       b.blk1 = (int32_t)blocks;
       for (int64_t t = 0; t < tiles; ++t)
-        for (int e = 0; e < gr.arity; ++e) em_part.push_back({zof(0, e), b.part_off + t * gr.arity + e});
+        for (int e = 0; e < gr.arity; ++e) em.push_back({zof(0, e), b.dst_off + t * gr.arity + e});
       for (int64_t f = 0; f < gr.n; ++f)
         for (int e = 0; e < gr.arity; ++e) {
           P.upos[us] = b.m_off + (int64_t)e * b.nfp + f;
@@ -376,7 +380,6 @@ admm_status build_plan(admm_graph& g, Plan& P) {
           ++us;
         }
       P.algo_elems += (int64_t)gr.n * (2 * gr.arity + d + 3);
-      P.layout_elems += tiles * gr.arity;
     } else if (separable) {
       // ---------------- separable operators: one thread per slot ----------------
       b.mode = BM_GEN_SLOT;
@@ -387,6 +390,8 @@ admm_status build_plan(admm_graph& g, Plan& P) {
       b.nslot = 1;
       const int64_t i0 = (int64_t)P.idx.size();
       P.idx.resize(i0 + b.nfp, 0);
+      b.dst_off = (int64_t)P.idx.size();
+      P.idx.resize(P.idx.size() + b.nfp, -1);
       P.par.resize(P.par.size() + 2 * (size_t)b.nfp, 0.0);
       double* par = P.par.data() + b.par_off;
       int64_t s = 0;
@@ -411,7 +416,7 @@ admm_status build_plan(admm_graph& g, Plan& P) {
             P.uz[us] = (int32_t)zi;
             deg[zi]++;
             ++us;
-            em_m.push_back({zi, b.m_off + s});
+            em.push_back({zi, b.dst_off + s});
           }
         }
       }
@@ -515,6 +520,8 @@ admm_status build_plan(admm_graph& g, Plan& P) {
         }
       }
       P.n_m += (int64_t)b.nslot * b.nfp;
+      b.dst_off = (int64_t)P.idx.size();
+      P.idx.resize(P.idx.size() + (int64_t)b.nslot * b.nfp, -1);
       for (int64_t f = 0; f < gr.n; ++f) {
         int s = 0;
         for (int e = 0; e < gr.arity; ++e) {
@@ -526,7 +533,7 @@ admm_status build_plan(admm_graph& g, Plan& P) {
             P.uz[us] = (int32_t)zi;
             deg[zi]++;
             ++us;
-            em_m.push_back({zi, pos});
+            em.push_back({zi, b.dst_off + (int64_t)s * b.nfp + f});
           }
         }
       }
@@ -541,24 +548,24 @@ admm_status build_plan(admm_graph& g, Plan& P) {
   if (us != g.n_slots) return admmi::set_err(ADMM_E_ARG, "internal: slot count mismatch");
   if (blocks > 0x7fffffff) return admmi::set_err(ADMM_E_UNSUPPORTED, "graph too large for one launch");
   P.xblocks = blocks;
-  // pool = [partials | m regions | x regions]: shift m offsets past partials
+  // Contribution positions: counting sort by z index (emission order kept
+  // within a scalar), so that each scalar's contributions are contiguous.
+  P.n_zc = (int64_t)em.size();
+  std::vector<int64_t> cnt(g.nz + 1, 0);
+  for (auto& e : em) cnt[e.z + 1]++;
+  for (int64_t i = 0; i < g.nz; ++i) cnt[i + 1] += cnt[i];
+  {
+    std::vector<int64_t> fill(cnt.begin(), cnt.end() - 1);
+    for (auto& e : em) P.idx[e.key] = (int32_t)(fill[e.z]++);
+  }
+  // pool = [contributions | m regions | x regions]
   for (BucketDesc& b : P.bt) {
-    b.m_off += P.n_part;
+    b.m_off += P.n_zc;
     b.x_off = b.m_off + P.n_m;
   }
-  for (auto& v : P.upos) v += P.n_part;
-  for (auto& e : em_m) e.pos += P.n_part;
-  if (P.n_part + P.n_m > 0xffffffffLL)
-    return admmi::set_err(ADMM_E_UNSUPPORTED, "more than 2^32 state elements");
-  // contribution lists: counting sort by z index, emission order kept
-  std::vector<int64_t> cnt(g.nz + 1, 0);
-  for (auto& e : em_part) cnt[e.z + 1]++;
-  for (auto& e : em_m) cnt[e.z + 1]++;
-  for (int64_t i = 0; i < g.nz; ++i) cnt[i + 1] += cnt[i];
-  P.csr.assign(cnt[g.nz], 0);
-  std::vector<int64_t> fill(cnt.begin(), cnt.end() - 1);
-  for (auto& e : em_part) P.csr[fill[e.z]++] = (uint32_t)e.pos;
-  for (auto& e : em_m) P.csr[fill[e.z]++] = (uint32_t)e.pos;
+  for (auto& v : P.upos) v += P.n_zc;
+  if (P.n_zc + 2 * P.n_m > 0x7fffffffLL)
+    return admmi::set_err(ADMM_E_UNSUPPORTED, "more than 2^31 pool elements");
   for (int64_t zi = 0; zi < g.nz; ++zi) {
     const int64_t len = cnt[zi + 1] - cnt[zi];
     if (len > LANE_MAX) {
@@ -573,8 +580,9 @@ admm_status build_plan(admm_graph& g, Plan& P) {
       P.deg_l.push_back((double)std::max<int64_t>(deg[zi], 1));
     }
   }
-  P.layout_elems += (int64_t)P.csr.size();
-  P.layout_idx_bytes += (int64_t)P.csr.size() * 4;
+  // each contribution is written once and read once; its destination index read once
+  P.layout_elems += 2 * P.n_zc;
+  P.layout_idx_bytes += P.n_zc * 4;
   return ADMM_OK;
 }
 
@@ -595,7 +603,6 @@ struct Engine : EngineBase {
   BucketDesc* bt = nullptr;
   T* z[2] = {nullptr, nullptr};
   int zc = 0;
-  uint32_t* csr = nullptr;
   int32_t *var_w = nullptr, *var_l = nullptr;
   int64_t *rng_w = nullptr, *rng_l = nullptr;
   T *deg_w = nullptr, *deg_l = nullptr;
@@ -661,7 +668,7 @@ struct Engine : EngineBase {
     nz = (int64_t)z0.size();
     xdelta = P.n_m;
     admm_status s;
-    const int64_t pool_n = P.n_part + 2 * P.n_m;
+    const int64_t pool_n = P.n_zc + 2 * P.n_m;
     if ((s = alloc(&pool, pool_n))) return s;
     ADMM_HIP(hipMemset(pool, 0, (size_t)std::max<int64_t>(pool_n, 1) * sizeof(T)));
     if ((s = put_conv(&par, P.par))) return s;
@@ -669,7 +676,6 @@ struct Engine : EngineBase {
     if ((s = put(&bt, P.bt))) return s;
     if ((s = alloc(&z[0], nz))) return s;
     if ((s = alloc(&z[1], nz))) return s;
-    if ((s = put(&csr, P.csr))) return s;
     if ((s = put(&var_w, P.var_w))) return s;
     if ((s = put(&var_l, P.var_l))) return s;
     if ((s = put(&rng_w, P.rng_w))) return s;
@@ -742,7 +748,6 @@ struct Engine : EngineBase {
   void launch_z(int check, hipStream_t st, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
     ZArgs<T> a;
     a.pool = pool;
-    a.csr = csr;
     a.var_w = var_w;
     a.rng_w = rng_w;
     a.deg_w = deg_w;
@@ -973,6 +978,21 @@ admm_status admm_graph_set_alpha(admm_graph* g, double alpha) {
   return ADMM_OK;
 }
 
+admm_status admm_graph_set_option(admm_graph* g, int32_t option, int64_t value) {
+  admmi::clear_err();
+  if (admm_status s = check_graph(g)) return s;
+  if (g->state != 0) return admmi::set_err(ADMM_E_STATE, "graph already finalized");
+  switch (option) {
+    case ADMM_OPT_PAIR_ROWS:
+      if (value != 0 && value != 16 && value != 32 && value != 64)
+        return admmi::set_err(ADMM_E_ARG, "pair tile rows must be 0, 16, 32 or 64");
+      g->pair_rows = (int32_t)value;
+      return ADMM_OK;
+    default:
+      return admmi::set_err(ADMM_E_ARG, "unknown option %d", option);
+  }
+}
+
 admm_status admm_graph_finalize(admm_graph* g, int32_t device) {
   admmi::clear_err();
   if (admm_status s = check_graph(g)) return s;
@@ -988,10 +1008,10 @@ admm_status admm_graph_finalize(admm_graph* g, int32_t device) {
   I.n_slots = g->n_slots;
   I.n_buckets = (int64_t)P.bt.size();
   I.n_pair_tiles = P.n_pair_tiles;
-  I.n_contributions = (int64_t)P.csr.size();
+  I.n_contributions = P.n_zc;
   I.precision = g->precision;
   I.alpha_is_one = g->alpha == 1.0;
-  I.state_bytes = (P.n_part + 2 * P.n_m) * es;
+  I.state_bytes = (P.n_zc + 2 * P.n_m) * es;
   // algorithmic: state read + write per slot (m; plus x when alpha != 1) and
   // per-factor prox data; layout: indices, partial sums and their reads.
   I.algo_bytes_per_iter = P.algo_elems * es * (g->alpha == 1.0 ? 1 : 2);
@@ -1019,7 +1039,6 @@ admm_status admm_graph_finalize(admm_graph* g, int32_t device) {
   // host copies only needed for the layout; keep user slot map on device only
   g->plan.idx.clear(); g->plan.idx.shrink_to_fit();
   g->plan.par.clear(); g->plan.par.shrink_to_fit();
-  g->plan.csr.clear(); g->plan.csr.shrink_to_fit();
   g->plan.upos.clear(); g->plan.upos.shrink_to_fit();
   g->plan.uz.clear(); g->plan.uz.shrink_to_fit();
   return ADMM_OK;

@@ -6,9 +6,13 @@
 //           bucket's proximal operator (eq. (3), appendix closed forms),
 //           forms m = x + u and writes the new state.  Structured buckets
 //           also emit per-tile partial sums of m for the z-update.
-//   z-pass  z_b = (sum of the contributions listed for b) / deg(b), summed
-//           in a fixed order (one lane per short list, a wavefront tree per
-//           long list): deterministic, no atomics.
+//   z-pass  z_b = (sum of b's contributions) / deg(b), summed in a fixed
+//           order (one lane per short list, a wavefront tree per long list):
+//           deterministic, no atomics.
+// Contributions (per-tile partial sums, or m itself for unstructured
+// buckets) are written by the x-pass straight into a z-major buffer at the
+// start of the pool, through destination tables built at finalize, so each
+// variable's contributions are contiguous for the z-pass.
 // State per slot: with alpha == 1 only m is kept (u = m - z, n = 2z - m);
 // otherwise m and x are kept and u = (m - x) + alpha (x - z).
 #pragma once
@@ -46,8 +50,10 @@ struct BucketDesc {
   int64_t nfp;          // SoA row stride
   int32_t arity, nslot; // edges / scalar slots per factor
   int32_t d, nn, mm, dmax;  // hinge d (and its register bound); lindyn n, m
-  int32_t E, NB;        // pair layout: entities, entity blocks
-  int64_t m_off, x_off, part_off;  // element offsets in the pool
+  int32_t E, NB;        // pair layout: entities, column blocks
+  int32_t rb, pad_;     // pair layout: entities per row block (16, 32 or 64)
+  int64_t m_off, x_off;  // element offsets of the state regions in the pool
+  int64_t dst_off;      // index-buffer offset of the contribution destinations
   int64_t idx_off;      // offset in the int32 index buffer
   int64_t par_off;      // element offset in the parameter buffer
 };
@@ -67,7 +73,6 @@ struct XArgs {
 template <typename T>
 struct ZArgs {
   const T* pool;
-  const uint32_t* csr;
   const int32_t* var_w;
   const int64_t* rng_w;
   const T* deg_w;
@@ -158,25 +163,30 @@ __device__ __forceinline__ void prox_wall(T* v, T qx, T qy, T qv, T ik) {
 }
 
 // ---------------------------------------------------------------------------
-// Dense pairwise non-overlap tiles.  Tile (I, J), I <= J, holds the pairs
-// (I*64 + li, J*64 + lj); storage [slot 0..5][li*64 + lj] with slots
+// Dense pairwise non-overlap tiles.  Tile (I, J) holds the pairs
+// (e_i, e_j) = (I*RB + li, J*64 + lj), li < RB, lj < 64, of which those with
+// e_i < e_j < E are real factors; storage [slot 0..5][li*64 + lj] with slots
 // (c_i.x, c_i.y, r_i, c_j.x, c_j.y, r_j).  Thread t owns column lj = t % 64
-// and rows 16*(t/64) .. +15; rows are summed across the wavefront, columns
-// in registers and then across the four wavefronts.
-// Partials per tile: [row li][3] then [col lj][3].
+// and rows (t/64)*RB/4 .. +RB/4-1; rows are summed across the wavefront,
+// columns in registers and then across the four wavefronts.
+// Partials per tile: [row li][3] (RB rows) then [col lj][3] (64 columns).
 // ---------------------------------------------------------------------------
-template <typename T, bool A1, int MODE>
+template <typename T, bool A1, int MODE, int RB>
 __device__ __forceinline__ void xpass_pair(const XArgs<T>& a, const BucketDesc& b, int tile) {
-  __shared__ T zrow[PB * 3];
-  __shared__ T zcol[PB * 3];
-  __shared__ T cacc[NT / 64][PB * 3];
+  constexpr int CB = PB;              // columns per tile
+  constexpr int PRR = RB * CB / NT;   // rows per thread
+  constexpr int TSZ = RB * CB;        // pairs per tile
+  __shared__ T zrow[RB * 3];
+  __shared__ T zcol[CB * 3];
+  __shared__ T cacc[NT / 64][CB * 3];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int32_t* tiles = a.idx + b.idx_off;
   const int32_t* ent = tiles + 2 * b.n;
   const int I = tiles[2 * tile], J = tiles[2 * tile + 1];
-  if (t < 2 * PB) {
-    const int l = t & (PB - 1);
-    const int e = ((t < PB) ? I : J) * PB + l;
+  if (t < RB + CB) {
+    const bool isrow = t < RB;
+    const int l = isrow ? t : t - RB;
+    const int e = isrow ? I * RB + l : J * CB + l;
     T cx = T(0), cy = T(0), r = T(0);
     if (e < b.E) {
       const int zc = ent[2 * e], zr = ent[2 * e + 1];
@@ -184,35 +194,35 @@ __device__ __forceinline__ void xpass_pair(const XArgs<T>& a, const BucketDesc& 
       cy = a.z[zc + 1];
       r = a.z[zr];
     }
-    T* dst = (t < PB) ? zrow : zcol;
+    T* dst = isrow ? zrow : zcol;
     dst[l * 3 + 0] = cx;
     dst[l * 3 + 1] = cy;
     dst[l * 3 + 2] = r;
   }
   __syncthreads();
   const int lj = lane;
-  const int ej = J * PB + lj;
+  const int ej = J * CB + lj;
   const T zj0 = zcol[lj * 3 + 0], zj1 = zcol[lj * 3 + 1], zj2 = zcol[lj * 3 + 2];
-  constexpr int64_t TS = 6 * PB * PB;
+  constexpr int64_t TS = 6 * (int64_t)TSZ;
   T* mt = a.pool + b.m_off + (int64_t)tile * TS;
   T* xt = a.pool + b.x_off + (int64_t)tile * TS;
   T ca0 = T(0), ca1 = T(0), ca2 = T(0);
   T rv0 = T(0), rv1 = T(0), rv2 = T(0);
   T rmax = T(0);
 #pragma unroll
-  for (int k = 0; k < PR; ++k) {
-    const int li = w * PR + k;
-    const int ei = I * PB + li;
-    const bool valid = (ei < b.E) && (ej < b.E) && (I != J || li < lj);
-    const int p = li * PB + lj;
+  for (int k = 0; k < PRR; ++k) {
+    const int li = w * PRR + k;
+    const int ei = I * RB + li;
+    const bool valid = (ei < ej) && (ej < b.E);
+    const int p = li * CB + lj;
     const T zz[6] = {zrow[li * 3 + 0], zrow[li * 3 + 1], zrow[li * 3 + 2], zj0, zj1, zj2};
     T mv[6];
 #pragma unroll
-    for (int s = 0; s < 6; ++s) mv[s] = mt[s * PB * PB + p];
+    for (int s = 0; s < 6; ++s) mv[s] = mt[s * TSZ + p];
     if constexpr (MODE == PM_RESID) {
 #pragma unroll
       for (int s = 0; s < 6; ++s) {
-        const T xv = xt[s * PB * PB + p];
+        const T xv = xt[s * TSZ + p];
         if (valid) rmax = tmax(rmax, tabs(xv - zz[s]));
       }
     } else {
@@ -220,7 +230,7 @@ __device__ __forceinline__ void xpass_pair(const XArgs<T>& a, const BucketDesc& 
 #pragma unroll
       for (int s = 0; s < 6; ++s) {
         T xo = T(0);
-        if constexpr (!A1) xo = xt[s * PB * PB + p];
+        if constexpr (!A1) xo = xt[s * TSZ + p];
         state_un<T, A1>(mv[s], xo, zz[s], a.alpha, u[s], v[s]);
       }
       prox_nonoverlap(v);
@@ -230,8 +240,8 @@ __device__ __forceinline__ void xpass_pair(const XArgs<T>& a, const BucketDesc& 
       if (valid) {
 #pragma unroll
         for (int s = 0; s < 6; ++s) {
-          mt[s * PB * PB + p] = mn[s];
-          if constexpr (!A1 || MODE == PM_SAVE) xt[s * PB * PB + p] = v[s];
+          mt[s * TSZ + p] = mn[s];
+          if constexpr (!A1 || MODE == PM_SAVE) xt[s * TSZ + p] = v[s];
         }
       }
       ca0 += valid ? mn[3] : T(0);
@@ -250,22 +260,26 @@ __device__ __forceinline__ void xpass_pair(const XArgs<T>& a, const BucketDesc& 
   if constexpr (MODE == PM_RESID) {
     block_max_store(rmax, a.blockmax);
   } else {
-    T* part = a.pool + b.part_off + (int64_t)tile * (6 * PB);
-    if (lane < PR) {
-      const int li = w * PR + lane;
-      part[li * 3 + 0] = rv0;
-      part[li * 3 + 1] = rv1;
-      part[li * 3 + 2] = rv2;
+    const int32_t* dst = a.idx + b.dst_off + (int64_t)tile * (3 * (RB + CB));
+    if (lane < PRR) {
+      const int li = w * PRR + lane;
+      const int d0 = dst[li * 3];
+      if (d0 >= 0) {
+        a.pool[d0] = rv0;
+        a.pool[dst[li * 3 + 1]] = rv1;
+        a.pool[dst[li * 3 + 2]] = rv2;
+      }
     }
     cacc[w][lj * 3 + 0] = ca0;
     cacc[w][lj * 3 + 1] = ca1;
     cacc[w][lj * 3 + 2] = ca2;
     __syncthreads();
-    if (t < PB * 3) {
+    if (t < CB * 3) {
       T s = cacc[0][t];
 #pragma unroll
       for (int q = 1; q < NT / 64; ++q) s += cacc[q][t];
-      part[3 * PB + t] = s;
+      const int d = dst[3 * RB + t];
+      if (d >= 0) a.pool[d] = s;
     }
   }
 }
@@ -329,6 +343,7 @@ __device__ __forceinline__ void xpass_hinge(const XArgs<T>& a, const BucketDesc&
     if (valid) {
       M[d * nfp + ff] = mnb;
       if constexpr (!A1 || MODE == PM_SAVE) X[d * nfp + ff] = xb;
+      if constexpr (!UNIF) a.pool[a.idx[b.dst_off + d * nfp + ff]] = mnb;
     }
 #pragma unroll
     for (int k = 0; k < DM; ++k) {
@@ -338,6 +353,7 @@ __device__ __forceinline__ void xpass_hinge(const XArgs<T>& a, const BucketDesc&
         if (valid) {
           M[k * nfp + ff] = mk;
           if constexpr (!A1 || MODE == PM_SAVE) X[k * nfp + ff] = xk;
+          if constexpr (!UNIF) a.pool[a.idx[b.dst_off + k * nfp + ff]] = mk;
         }
         if constexpr (UNIF) {
           const T s = admmi::wave_sum(valid ? mk : T(0));
@@ -353,7 +369,7 @@ __device__ __forceinline__ void xpass_hinge(const XArgs<T>& a, const BucketDesc&
         T acc = wsum[0][t];
 #pragma unroll
         for (int q = 1; q < NT / 64; ++q) acc += wsum[q][t];
-        a.pool[b.part_off + (int64_t)blk * (d + 1) + t] = acc;
+        a.pool[a.idx[b.dst_off + (int64_t)blk * (d + 1) + t]] = acc;
       }
     }
   }
@@ -394,6 +410,7 @@ __device__ __forceinline__ void xpass_slot(const XArgs<T>& a, const BucketDesc& 
       }
       M[s] = x + u;
       if constexpr (!A1 || MODE == PM_SAVE) X[s] = x;
+      a.pool[a.idx[b.dst_off + s]] = x + u;
     }
   }
   if constexpr (MODE == PM_RESID) block_max_store(rmax, a.blockmax);
@@ -442,10 +459,13 @@ __device__ __forceinline__ void gen_store(const XArgs<T>& a, const BucketDesc& b
                                           const T (&u)[NSL], const T (&v)[NSL]) {
   T* M = a.pool + b.m_off;
   T* X = a.pool + b.x_off;
+  const int32_t* dst = a.idx + b.dst_off;
 #pragma unroll
   for (int s = 0; s < NSL; ++s) {
-    M[s * b.nfp + f] = v[s] + u[s];
+    const T mn = v[s] + u[s];
+    M[s * b.nfp + f] = mn;
     if constexpr (!A1 || MODE == PM_SAVE) X[s * b.nfp + f] = v[s];
+    a.pool[dst[s * b.nfp + f]] = mn;
   }
 }
 
@@ -566,6 +586,7 @@ __device__ __forceinline__ void xpass_lindyn(const XArgs<T>& a, const BucketDesc
           va[j] -= s;
           M[j * nfp + f] = va[j] + ua[j];
           if constexpr (!A1 || MODE == PM_SAVE) X[j * nfp + f] = va[j];
+          a.pool[a.idx[b.dst_off + j * nfp + f]] = va[j] + ua[j];
         }
       }
 #pragma unroll
@@ -574,6 +595,7 @@ __device__ __forceinline__ void xpass_lindyn(const XArgs<T>& a, const BucketDesc
           vb[r] += vv[r];
           M[(k + r) * nfp + f] = vb[r] + ub[r];
           if constexpr (!A1 || MODE == PM_SAVE) X[(k + r) * nfp + f] = vb[r];
+          a.pool[a.idx[b.dst_off + (k + r) * nfp + f]] = vb[r] + ub[r];
         }
       }
     }
@@ -602,7 +624,12 @@ __global__ __launch_bounds__(NT) void xpass_kernel(XArgs<T> a) {
   const BucketDesc b = a.bt[bi];
   const int local = blk - b.blk0;
   if ((FS & FT_PAIR) && b.mode == BM_PAIR) {
-    xpass_pair<T, A1, MODE>(a, b, local);
+    if (b.rb == 16)
+      xpass_pair<T, A1, MODE, 16>(a, b, local);
+    else if (b.rb == 32)
+      xpass_pair<T, A1, MODE, 32>(a, b, local);
+    else
+      xpass_pair<T, A1, MODE, 64>(a, b, local);
   } else if ((FS & (FT_UHINGE | FT_WIDE)) && b.mode == BM_UNIF_HINGE) {
     if ((FS & FT_UHINGE) && b.dmax <= 32)
       xpass_hinge<T, A1, MODE, true, 32>(a, b, local);
@@ -637,7 +664,7 @@ __global__ __launch_bounds__(NT) void zpass_kernel(ZArgs<T> a) {
     T s = T(0);
     if (ok) {
       const int64_t o1 = a.rng_w[2 * k + 1];
-      for (int64_t j = a.rng_w[2 * k] + lane; j < o1; j += 64) s += a.pool[a.csr[j]];
+      for (int64_t j = a.rng_w[2 * k] + lane; j < o1; j += 64) s += a.pool[j];
     }
     s = admmi::wave_sum(s);
     if (ok && lane == 0) {
@@ -654,7 +681,7 @@ __global__ __launch_bounds__(NT) void zpass_kernel(ZArgs<T> a) {
       T zn = a.zin[zi];
       if (o1 > o0) {
         T s = T(0);
-        for (int64_t j = o0; j < o1; ++j) s += a.pool[a.csr[j]];
+        for (int64_t j = o0; j < o1; ++j) s += a.pool[j];
         zn = s / a.deg_l[k];
       }
       a.zout[zi] = zn;

@@ -30,7 +30,7 @@ __device__ __forceinline__ unsigned short f2bf(float f) {
   return (unsigned short)(u >> 16);
 }
 
-enum Epi : int { EPI_PLAIN = 0, EPI_BIAS = 1, EPI_BIAS_RELU = 2, EPI_MASK = 3 };
+enum Epi : int { EPI_PLAIN = 0, EPI_BIAS = 1, EPI_BIAS_RELU = 2, EPI_MASK = 3, EPI_BIAS_AFFINE = 4 };
 
 // C[M x N] = sum_k A(m,k) B(k,n); A(m,k) = TA ? A[k*lda+m] : A[m*lda+k],
 // B(k,n) = TB ? B[n*ldb+k] : B[k*ldb+n].  Epilogue per EPI.
@@ -41,7 +41,9 @@ __global__ __launch_bounds__(GT) void gemm_kernel(int M, int N, int K, const flo
                                                  int lda, const float* __restrict__ B, int ldb,
                                                  float* __restrict__ C, int ldc,
                                                  const float* __restrict__ bias,
-                                                 const float* __restrict__ mask, int ldm) {
+                                                 const float* __restrict__ mask, int ldm,
+                                                 const float* __restrict__ mu,
+                                                 const float* __restrict__ sd) {
   __shared__ unsigned short As[BM][BK + 4];
   __shared__ unsigned short Bs[BK][BN + 4];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
@@ -107,7 +109,8 @@ __global__ __launch_bounds__(GT) void gemm_kernel(int M, int N, int K, const flo
         const int row = m0 + wm + i * 16 + (lane >> 4) * 4 + q;
         if (row < M && col < N) {
           float v = acc[i][j][q];
-          if (EPI == EPI_BIAS || EPI == EPI_BIAS_RELU) v += bias[col];
+          if (EPI == EPI_BIAS || EPI == EPI_BIAS_RELU || EPI == EPI_BIAS_AFFINE) v += bias[col];
+          if (EPI == EPI_BIAS_AFFINE) v = mu[col] + sd[col] * v;
           if (EPI == EPI_BIAS_RELU) v = v > 0.f ? v : 0.f;
           if (EPI == EPI_MASK) v = mask[(int64_t)row * ldm + col] > 0.f ? v : 0.f;
           C[(int64_t)row * ldc + col] = v;
@@ -116,13 +119,18 @@ __global__ __launch_bounds__(GT) void gemm_kernel(int M, int N, int K, const flo
     }
 }
 
-// dY = 2 (y - target) / (rows * cols); per-block partial sums of (y - t)^2.
-__global__ __launch_bounds__(256) void mse_grad_kernel(int64_t n, const float* y, const float* tg,
-                                                       float scale, float* dy, float* part) {
+// Loss on normalised outputs: with yh the network's raw output and
+// th = (target - mu) / sd per column, dY = 2 (yh - th) / (rows * cols);
+// per-block partial sums of (yh - th)^2.
+__global__ __launch_bounds__(256) void mse_grad_kernel(int64_t n, int cols, const float* y,
+                                                       const float* tg, const float* mu,
+                                                       const float* sd, float scale, float* dy,
+                                                       float* part) {
   __shared__ float red[256];
   float s = 0.f;
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
-    const float d = y[i] - tg[i];
+    const int c = (int)(i % cols);
+    const float d = y[i] - (tg[i] - mu[c]) / sd[c];
     dy[i] = 2.f * d * scale;
     s += d * d;
   }
@@ -141,6 +149,30 @@ __global__ void finish_loss_kernel(int nb, const float* part, float scale, float
     for (int i = 0; i < nb; ++i) s += part[i];
     *loss = s * scale;
   }
+}
+
+// Per-column mean and standard deviation of a [rows][cols] array, FP64
+// accumulation, rows in order; sd is floored at sd_min.
+__global__ void colstats_kernel(int64_t rows, int cols, const float* a, float sd_min, float* mu,
+                                float* sd) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= cols) return;
+  double s = 0.0;
+  for (int64_t r = 0; r < rows; ++r) s += (double)a[r * cols + c];
+  const double m = s / (double)rows;
+  double q = 0.0;
+  for (int64_t r = 0; r < rows; ++r) {
+    const double d = (double)a[r * cols + c] - m;
+    q += d * d;
+  }
+  const double v = sqrt(q / (double)rows);
+  mu[c] = (float)m;
+  sd[c] = (float)(v > sd_min ? v : sd_min);
+}
+
+__global__ void fill_kernel(int n, float v, float* a) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = v;
 }
 
 // db[c] = sum_r dY[r][c], one thread per column, rows in order.
@@ -175,6 +207,7 @@ struct admm_mlp {
   float *p = nullptr, *g = nullptr, *am = nullptr, *av = nullptr;
   float *h1 = nullptr, *h2 = nullptr, *y = nullptr, *dy = nullptr, *dh1 = nullptr, *dh2 = nullptr;
   float* part = nullptr;
+  float *mu = nullptr, *sd = nullptr;  // fixed output affine y = mu + sd * yhat
   int64_t step = 0;
   std::vector<void*> allocs;
   ~admm_mlp() {
@@ -197,27 +230,36 @@ admm_status mlp_alloc(admm_mlp* n, float** q, int64_t count) {
 
 template <bool TA, bool TB, int EPI>
 void gemm(int M, int N, int K, const float* A, int lda, const float* B, int ldb, float* C, int ldc,
-          const float* bias, const float* mask, int ldm, hipStream_t st) {
+          const float* bias, const float* mask, int ldm, hipStream_t st,
+          const float* mu = nullptr, const float* sd = nullptr) {
   dim3 grid((N + BN - 1) / BN, (M + BM - 1) / BM);
-  gemm_kernel<TA, TB, EPI><<<grid, GT, 0, st>>>(M, N, K, A, lda, B, ldb, C, ldc, bias, mask, ldm);
+  gemm_kernel<TA, TB, EPI><<<grid, GT, 0, st>>>(M, N, K, A, lda, B, ldb, C, ldc, bias, mask, ldm,
+                                                 mu, sd);
 }
 
-// forward: h1 = relu(x W1^T + b1), h2 = relu(h1 W2^T + b2), y = h2 W3^T + b3
-void forward(admm_mlp* n, const float* x, int batch, float* y, hipStream_t st) {
+// forward: h1 = relu(x W1^T + b1), h2 = relu(h1 W2^T + b2),
+// yhat = h2 W3^T + b3; with denorm, y = mu + sd * yhat.
+void forward(admm_mlp* n, const float* x, int batch, float* y, hipStream_t st, bool denorm) {
   gemm<false, true, EPI_BIAS_RELU>(batch, n->hid, n->n_in, x, n->n_in, n->p + n->oW1, n->n_in, n->h1,
                                    n->hid, n->p + n->ob1, nullptr, 0, st);
   gemm<false, true, EPI_BIAS_RELU>(batch, n->hid, n->hid, n->h1, n->hid, n->p + n->oW2, n->hid, n->h2,
                                    n->hid, n->p + n->ob2, nullptr, 0, st);
-  gemm<false, true, EPI_BIAS>(batch, n->n_out, n->hid, n->h2, n->hid, n->p + n->oW3, n->hid, y,
-                              n->n_out, n->p + n->ob3, nullptr, 0, st);
+  if (denorm)
+    gemm<false, true, EPI_BIAS_AFFINE>(batch, n->n_out, n->hid, n->h2, n->hid, n->p + n->oW3,
+                                       n->hid, y, n->n_out, n->p + n->ob3, nullptr, 0, st, n->mu,
+                                       n->sd);
+  else
+    gemm<false, true, EPI_BIAS>(batch, n->n_out, n->hid, n->h2, n->hid, n->p + n->oW3, n->hid, y,
+                                n->n_out, n->p + n->ob3, nullptr, 0, st);
 }
 
 // gradients of mean((y - t)^2) into n->g; loss (device scalar) when non-null
 void backward(admm_mlp* n, const float* x, const float* tg, int batch, float* loss, hipStream_t st) {
-  forward(n, x, batch, n->y, st);
+  forward(n, x, batch, n->y, st, false);
   const int64_t ny = (int64_t)batch * n->n_out;
   const float scale = 1.f / (float)ny;
-  mse_grad_kernel<<<LOSS_BLOCKS, 256, 0, st>>>(ny, n->y, tg, scale, n->dy, n->part);
+  mse_grad_kernel<<<LOSS_BLOCKS, 256, 0, st>>>(ny, n->n_out, n->y, tg, n->mu, n->sd, scale, n->dy,
+                                                n->part);
   if (loss) finish_loss_kernel<<<1, 64, 0, st>>>(LOSS_BLOCKS, n->part, scale, loss);
   float* g = n->g;
   // layer 3
@@ -277,6 +319,12 @@ admm_status admm_mlp_create(int32_t n_in, int32_t hidden, int32_t n_out, int32_t
   if ((s = mlp_alloc(n.get(), &n->dh1, B * hidden))) return s;
   if ((s = mlp_alloc(n.get(), &n->dh2, B * hidden))) return s;
   if ((s = mlp_alloc(n.get(), &n->part, LOSS_BLOCKS))) return s;
+  if ((s = mlp_alloc(n.get(), &n->mu, n_out))) return s;
+  if ((s = mlp_alloc(n.get(), &n->sd, n_out))) return s;
+  fill_kernel<<<(n_out + 255) / 256, 256>>>(n_out, 0.f, n->mu);
+  fill_kernel<<<(n_out + 255) / 256, 256>>>(n_out, 1.f, n->sd);
+  ADMM_HIP(hipGetLastError());
+  ADMM_HIP(hipDeviceSynchronize());
   ADMM_HIP(hipMemset(n->p, 0, n->n_params * sizeof(float)));
   ADMM_HIP(hipMemset(n->am, 0, n->n_params * sizeof(float)));
   ADMM_HIP(hipMemset(n->av, 0, n->n_params * sizeof(float)));
@@ -310,7 +358,7 @@ admm_status admm_mlp_forward(admm_mlp* n, const float* x, int32_t batch, float* 
   if (!n || !x || !y) return admmi::set_err(ADMM_E_ARG, "NULL argument");
   if (batch < 1 || batch > n->max_batch) return admmi::set_err(ADMM_E_ARG, "batch out of [1, max_batch]");
   ADMM_HIP(hipSetDevice(n->device));
-  forward(n, x, batch, y, (hipStream_t)stream);
+  forward(n, x, batch, y, (hipStream_t)stream, true);
   ADMM_HIP(hipGetLastError());
   return ADMM_OK;
 }
@@ -344,6 +392,38 @@ admm_status admm_mlp_train_step(admm_mlp* n, const float* x, const float* target
   adam_kernel<<<(unsigned)((n->n_params + 255) / 256), 256, 0, st>>>(n->n_params, n->p, n->g, n->am,
                                                                      n->av, lr, b1, b2, 1e-8f, c1, c2);
   ADMM_HIP(hipGetLastError());
+  return ADMM_OK;
+}
+
+admm_status admm_mlp_fit_output_scaling(admm_mlp* n, const float* targets, int64_t rows,
+                                        float sd_min, void* stream) {
+  admmi::clear_err();
+  if (!n || !targets || rows < 1) return admmi::set_err(ADMM_E_ARG, "bad arguments");
+  if (!(sd_min > 0.f)) return admmi::set_err(ADMM_E_ARG, "sd_min must be > 0");
+  ADMM_HIP(hipSetDevice(n->device));
+  colstats_kernel<<<(n->n_out + 63) / 64, 64, 0, (hipStream_t)stream>>>(rows, n->n_out, targets,
+                                                                        sd_min, n->mu, n->sd);
+  ADMM_HIP(hipGetLastError());
+  return ADMM_OK;
+}
+
+admm_status admm_mlp_set_output_scaling(admm_mlp* n, const float* mean, const float* sd) {
+  admmi::clear_err();
+  if (!n || !mean || !sd) return admmi::set_err(ADMM_E_ARG, "NULL argument");
+  for (int i = 0; i < n->n_out; ++i)
+    if (!(sd[i] > 0.f)) return admmi::set_err(ADMM_E_ARG, "sd must be > 0");
+  ADMM_HIP(hipSetDevice(n->device));
+  ADMM_HIP(hipMemcpy(n->mu, mean, n->n_out * sizeof(float), hipMemcpyHostToDevice));
+  ADMM_HIP(hipMemcpy(n->sd, sd, n->n_out * sizeof(float), hipMemcpyHostToDevice));
+  return ADMM_OK;
+}
+
+admm_status admm_mlp_get_output_scaling(admm_mlp* n, float* mean, float* sd) {
+  admmi::clear_err();
+  if (!n || !mean || !sd) return admmi::set_err(ADMM_E_ARG, "NULL argument");
+  ADMM_HIP(hipSetDevice(n->device));
+  ADMM_HIP(hipMemcpy(mean, n->mu, n->n_out * sizeof(float), hipMemcpyDeviceToHost));
+  ADMM_HIP(hipMemcpy(sd, n->sd, n->n_out * sizeof(float), hipMemcpyDeviceToHost));
   return ADMM_OK;
 }
 

@@ -34,6 +34,12 @@ def _setup():
     L.admm_mlp_grads.argtypes = [VP, VP, VP, ctypes.c_int32, VP, VP, VP]
     L.admm_mlp_train_step.restype = st
     L.admm_mlp_train_step.argtypes = [VP, VP, VP, ctypes.c_int32, ctypes.c_float, VP, VP]
+    L.admm_mlp_fit_output_scaling.restype = st
+    L.admm_mlp_fit_output_scaling.argtypes = [VP, VP, ctypes.c_int64, ctypes.c_float, VP]
+    L.admm_mlp_set_output_scaling.restype = st
+    L.admm_mlp_set_output_scaling.argtypes = [VP, FP, FP]
+    L.admm_mlp_get_output_scaling.restype = st
+    L.admm_mlp_get_output_scaling.argtypes = [VP, FP, FP]
     L.admm_mlp_destroy.restype = st
     L.admm_mlp_destroy.argtypes = [VP]
     _done = True
@@ -76,6 +82,23 @@ class MLP:
         a = np.zeros(self.n_params, np.float32)
         check(_setup().admm_mlp_get_params(self._h, a.ctypes.data_as(FP)))
         return a
+
+    def fit_output_scaling(self, targets, sd_min: float = 1e-6, stream=None):
+        check(_setup().admm_mlp_fit_output_scaling(self._h, _p(targets), int(targets.shape[0]),
+                                                   float(sd_min), _stream(stream)))
+
+    def set_output_scaling(self, mean, sd):
+        m = np.ascontiguousarray(mean, dtype=np.float32)
+        s = np.ascontiguousarray(sd, dtype=np.float32)
+        check(_setup().admm_mlp_set_output_scaling(self._h, m.ctypes.data_as(FP),
+                                                   s.ctypes.data_as(FP)))
+
+    def get_output_scaling(self):
+        m = np.zeros(self.n_out, np.float32)
+        s = np.zeros(self.n_out, np.float32)
+        check(_setup().admm_mlp_get_output_scaling(self._h, m.ctypes.data_as(FP),
+                                                   s.ctypes.data_as(FP)))
+        return m, s
 
     def forward(self, x, y, stream=None):
         check(_setup().admm_mlp_forward(self._h, _p(x), int(x.shape[0]), _p(y), _stream(stream)))

@@ -91,11 +91,13 @@ class WarmStart:
 
     def train(self, X, Z, epochs: int, lr: float = 1e-3, lr_final: Optional[float] = None,
               warmup: int = 200):
-        """Adam on contiguous minibatches of the (already i.i.d.) samples.
-        The learning rate rises linearly over the first `warmup` steps, then
-        decays geometrically to lr_final.  Returns the loss of the last
-        minibatch of each epoch."""
+        """Fit the network's fixed output affine to the targets' per-output
+        mean and spread, then run Adam on contiguous minibatches of the
+        (already i.i.d.) samples.  The learning rate rises linearly over the
+        first `warmup` steps, then decays geometrically to lr_final.
+        Returns the normalised loss of the last minibatch of each epoch."""
         torch = self.torch
+        self.net.fit_output_scaling(Z, sd_min=1e-4)
         N = X.shape[0]
         steps_per_epoch = N // self.batch
         total = epochs * steps_per_epoch

@@ -43,16 +43,22 @@ def _finalize_cpu(g):
         return e.status
 
 
-@pytest.mark.parametrize("name,tiles,buckets", [("packing_tri10", 1, 3),
-                                                ("packing_sq2000", 528, 3)])
-def test_packing_layout(name, tiles, buckets):
+def _expected_tiles(N, rb):
+    """Tiles of rb x 64 disks holding at least one pair i < j (brute force)."""
+    return len({(i // rb, j // 64) for i in range(N) for j in range(i + 1, N)})
+
+
+@pytest.mark.parametrize("name,N", [("packing_tri10", 10), ("packing_sq2000", 2000)])
+@pytest.mark.parametrize("rb", [16, 32, 64])
+def test_packing_layout(name, N, rb):
     p = W.workload(name)
-    g = A.Graph.from_problem(p, device=None)
+    g = A.Graph.from_problem(p, device=None, pair_rows=rb)
     assert _finalize_cpu(g) in (A.OK, A.E_NO_DEVICE)
     inf = g.info()
     assert inf["n_edges"] == p.n_edges and inf["n_slots"] == p.n_slots
     assert inf["n_factors"] == p.n_factors and inf["n_scalars"] == p.n_scalars
-    assert inf["n_pair_tiles"] == tiles and inf["n_buckets"] == buckets
+    assert inf["n_buckets"] == 3
+    assert inf["n_pair_tiles"] == _expected_tiles(N, rb)
     # algorithmic bytes: m read + write per slot, plus wall/radius/pair data
     assert inf["algo_bytes_per_iter"] >= 8 * p.n_slots
 
@@ -103,6 +109,8 @@ def test_validation_errors():
     g = A.Graph([1])
     _expect(A.E_ARG, g.set_rho, -1.0)
     _expect(A.E_ARG, g.set_alpha, 0.0)
+    _expect(A.E_ARG, g.set_option, A.OPT_PAIR_ROWS, 48)
+    _expect(A.E_ARG, g.set_option, 99, 1)
 
 
 def test_state_machine():

@@ -22,8 +22,8 @@ pytestmark = pytest.mark.gpu
 FP32, FP64 = A.FP32, A.FP64
 
 
-def _pair(problem, iters, precision, alpha=None, u0=None):
-    g = A.Graph.from_problem(problem, precision=precision, alpha=alpha)
+def _pair(problem, iters, precision, alpha=None, u0=None, pair_rows=0):
+    g = A.Graph.from_problem(problem, precision=precision, alpha=alpha, pair_rows=pair_rows)
     o = O.OracleGraph(problem, alpha=alpha)
     if u0 is not None:
         g.set_state(problem.z0, u0)
@@ -66,10 +66,10 @@ def _conditioning(problem, iters, prec, alpha=None, u0=None):
     return rel(b.z, a.z)
 
 
-def _traj(problem, iters, prec, tol, alpha=None, u0=None):
+def _traj(problem, iters, prec, tol, alpha=None, u0=None, pair_rows=0):
     sens = _conditioning(problem, iters, prec, alpha, u0)
     assert sens < tol / 20, f"test case ill-conditioned: oracle self-sensitivity {sens:.2e}"
-    g, o = _pair(problem, iters, prec, alpha=alpha, u0=u0)
+    g, o = _pair(problem, iters, prec, alpha=alpha, u0=u0, pair_rows=pair_rows)
     _check(g, o, tol)
     return g, o
 
@@ -93,13 +93,15 @@ def test_packing_triangle_10_final_objective_fp32():
     assert fg["max_violation"] < 1e-3
 
 
+@pytest.mark.parametrize("rb", [16, 32, 64])
 @pytest.mark.parametrize("N,shape,seed", [(2, "square", 1), (65, "square", 3),
                                           (130, "triangle", 7), (200, "square", 4)])
-def test_packing_tiles_ragged_fp64(N, shape, seed):
+def test_packing_tiles_ragged_fp64(N, shape, seed, rb):
     p = W.packing(N, shape, 0.3 / np.sqrt(N), seed=seed)
-    g, o = _traj(p, 15, FP64, 1e-9)
-    assert g.info()["n_pair_tiles"] == (((N + 63) // 64) * ((N + 63) // 64 + 1)) // 2
-    _one_step(p, 40, FP64, 1e-12)
+    g, o = _traj(p, 15, FP64, 1e-9, pair_rows=rb)
+    assert g.info()["n_pair_tiles"] == len({(i // rb, j // 64) for i in range(N)
+                                            for j in range(i + 1, N)})
+    _one_step(p, 40, FP64, 1e-12, pair_rows=rb)
 
 
 @pytest.mark.parametrize("N,seed", [(65, 12), (200, 12)])
@@ -215,12 +217,12 @@ def test_determinism_and_resume():
     assert np.array_equal(a.z(), d.z())
 
 
-def _one_step(problem, warm_iters, prec, tol, alpha=None):
+def _one_step(problem, warm_iters, prec, tol, alpha=None, pair_rows=0):
     """Run the GPU warm_iters iterations, hand its (z, u) to both sides and
     compare one further iteration element by element (no trajectory
     sensitivity involved), then check that the duals around every variable
     sum to zero (Algorithm 2 with u0 = 0 keeps that at any size)."""
-    g = A.Graph.from_problem(problem, precision=prec, alpha=alpha)
+    g = A.Graph.from_problem(problem, precision=prec, alpha=alpha, pair_rows=pair_rows)
     g.run(warm_iters)
     z, u = g.z(), g.u()
     g.set_state(z, u)
@@ -237,8 +239,9 @@ def _one_step(problem, warm_iters, prec, tol, alpha=None):
     assert np.max(np.abs(us) / scale) < (1e-12 if prec == FP64 else 1e-5)
 
 
-def test_full_size_packing_2000_one_step():
-    _one_step(W.workload("packing_sq2000"), 20, FP32, 1e-5)
+@pytest.mark.parametrize("rb", [16, 32, 64])
+def test_full_size_packing_2000_one_step(rb):
+    _one_step(W.workload("packing_sq2000"), 20, FP32, 1e-5, pair_rows=rb)
 
 
 def test_full_size_svm_100k_one_step():

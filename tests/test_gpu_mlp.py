@@ -79,3 +79,36 @@ def test_adam_step_matches_oracle_and_training_lowers_loss():
     net.grads(xd, td, None, loss)
     torch.cuda.synchronize()
     assert loss.item() < 0.3 * l0
+
+
+def test_output_scaling_forward_and_gradients():
+    """With a fixed output affine y = mean + sd * yhat the forward output is
+    denormalised and the loss is taken on (target - mean) / sd."""
+    n_in, hid, n_out, batch = 8, 64, 90, 200
+    net, flat = _net(n_in, hid, n_out, batch, 41)
+    rng = np.random.default_rng(8)
+    mean = rng.standard_normal(n_out).astype(np.float32) * 0.3
+    sd = (0.05 + rng.random(n_out)).astype(np.float32)
+    x = rng.standard_normal((batch, n_in)).astype(np.float32)
+    tg = (mean + sd * rng.standard_normal((batch, n_out))).astype(np.float32)
+    net.set_output_scaling(mean, sd)
+    xd, td = torch.tensor(x, device="cuda"), torch.tensor(tg, device="cuda")
+    y = torch.zeros((batch, n_out), device="cuda")
+    net.forward(xd, y)
+    g = torch.zeros(net.n_params, device="cuda")
+    loss = torch.zeros(1, device="cuda")
+    net.grads(xd, td, g, loss)
+    torch.cuda.synchronize()
+    params = WS.unflatten(flat, n_in, hid, n_out)
+    yo, _ = WS.mlp_forward(params, x.astype(np.float64), bf16=True, mean=mean, sd=sd)
+    assert rel(y.cpu().numpy(), yo) < 1e-3
+    lo, go = WS.mlp_loss_grad(params, x.astype(np.float64), tg.astype(np.float64), bf16=True,
+                              mean=mean.astype(np.float64), sd=sd.astype(np.float64))
+    assert abs(loss.item() - lo) < 1e-4 * abs(lo)
+    for a, b in zip(WS.unflatten(g.cpu().numpy(), n_in, hid, n_out), go):
+        assert rel(a, b) < 1e-3
+    # fitting the affine from data gives the columns' mean and spread
+    net.fit_output_scaling(td, sd_min=1e-6)
+    m2, s2 = net.get_output_scaling()
+    np.testing.assert_allclose(m2, tg.astype(np.float64).mean(0), rtol=1e-4, atol=1e-6)
+    np.testing.assert_allclose(s2, tg.astype(np.float64).std(0), rtol=1e-4)
