@@ -269,7 +269,8 @@ admm_status admm_mlp_get_params(admm_mlp* n, float* host);
  * mean) / sd)^2), so every output is learned to the same relative accuracy
  * and the bf16 products work on unit-scale values.  Default mean 0, sd 1.
  * fit: per-output mean and standard deviation (floored at sd_min) of a
- * device array targets [rows][n_out], FP64 accumulation, async. */
+ * device array targets [rows][n_out], FP64 accumulation in a fixed order;
+ * allocates a temporary workspace and synchronises the stream. */
 admm_status admm_mlp_fit_output_scaling(admm_mlp* n, const float* targets, int64_t rows,
                                         float sd_min, void* stream);
 admm_status admm_mlp_set_output_scaling(admm_mlp* n, const float* mean, const float* sd);

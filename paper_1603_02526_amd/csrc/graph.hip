@@ -662,7 +662,7 @@ struct Engine : EngineBase {
     }
     n_w = (int64_t)P.var_w.size();
     n_l = (int64_t)P.var_l.size();
-    nb_w = (n_w + (NT / 64) - 1) / (NT / 64);
+    nb_w = (n_w + ZPB - 1) / ZPB;
     zblocks = nb_w + (n_l + NT - 1) / NT;
     n_slots = (int64_t)P.upos.size();
     nz = (int64_t)z0.size();

@@ -651,23 +651,26 @@ __global__ __launch_bounds__(NT) void xpass_kernel(XArgs<T> a) {
   }
 }
 
-// z_b = sum(contributions) / deg(b).  Blocks [0, nb_w): four long lists
-// per block, one wavefront each (lanes stride the list, then a fixed
-// tree); remaining blocks: one short list per lane, summed in order.
+// z_b = sum(contributions) / deg(b).  Blocks [0, nb_w): sixteen lists of
+// more than LANE_MAX contributions per block, one 16-lane row each (lanes
+// stride the list, then a fixed DPP tree); remaining blocks: one short list
+// per lane, summed in order.
+constexpr int ZSEG = 16;                  // lanes per long list
+constexpr int ZPB = NT / ZSEG;            // long lists per block
 template <typename T>
 __global__ __launch_bounds__(NT) void zpass_kernel(ZArgs<T> a) {
   T dmax = T(0);
   if ((int)blockIdx.x < a.nb_w) {
-    const int lane = threadIdx.x & 63;
-    const int64_t k = (int64_t)blockIdx.x * (NT / 64) + (threadIdx.x >> 6);
+    const int sl = threadIdx.x & (ZSEG - 1);
+    const int64_t k = (int64_t)blockIdx.x * ZPB + (threadIdx.x / ZSEG);
     const bool ok = k < a.n_w;
     T s = T(0);
     if (ok) {
       const int64_t o1 = a.rng_w[2 * k + 1];
-      for (int64_t j = a.rng_w[2 * k] + lane; j < o1; j += 64) s += a.pool[j];
+      for (int64_t j = a.rng_w[2 * k] + sl; j < o1; j += ZSEG) s += a.pool[j];
     }
-    s = admmi::wave_sum(s);
-    if (ok && lane == 0) {
+    s = admmi::row16_sum(s);
+    if (ok && sl == 0) {
       const int zi = a.var_w[k];
       const T zn = s / a.deg_w[k];
       a.zout[zi] = zn;

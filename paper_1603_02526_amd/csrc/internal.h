@@ -51,6 +51,21 @@ __device__ __forceinline__ float wave_sum(float v) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
 }
 
+// Sum over each 16-lane row (DPP row), result in every lane of the row.
+__device__ __forceinline__ float row16_sum(float v) {
+  v += ADMM_DPP(v, 0xB1, 0xF);   // pairs
+  v += ADMM_DPP(v, 0x4E, 0xF);   // quads
+  v += ADMM_DPP(v, 0x141, 0xF);  // 8 lanes
+  v += ADMM_DPP(v, 0x140, 0xF);  // 16 lanes
+  return v;
+}
+
+__device__ __forceinline__ double row16_sum(double v) {
+#pragma unroll
+  for (int k = 8; k >= 1; k >>= 1) v += __shfl_xor(v, k, 16);
+  return v;
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int k = 32; k >= 1; k >>= 1) v += __shfl_xor(v, k, 64);

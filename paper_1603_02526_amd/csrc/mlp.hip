@@ -21,7 +21,7 @@ typedef short v4s __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
 constexpr int GT = 256;  // threads per GEMM workgroup (4 wavefronts)
-constexpr int BM = 64, BN = 64, BK = 16;
+constexpr int BM = 64, BN = 64, BK = 32;
 
 __device__ __forceinline__ unsigned short f2bf(float f) {
   unsigned int u = __float_as_uint(f);
@@ -35,10 +35,13 @@ enum Epi : int { EPI_PLAIN = 0, EPI_BIAS = 1, EPI_BIAS_RELU = 2, EPI_MASK = 3, E
 // C[M x N] = sum_k A(m,k) B(k,n); A(m,k) = TA ? A[k*lda+m] : A[m*lda+k],
 // B(k,n) = TB ? B[n*ldb+k] : B[k*ldb+n].  Epilogue per EPI.
 // Workgroup tile 64 x 64, each wavefront a 32 x 32 quarter as 2 x 2 MFMA
-// tiles of 16 x 16, K consumed 16 at a time through LDS.
+// tiles of 16 x 16, K consumed 32 at a time through LDS (two MFMA steps per
+// barrier).  Split K: workgroup z covers K range [z*kc, (z+1)*kc) and
+// writes its partial product to C + z*M*N (plain epilogue only).
 template <bool TA, bool TB, int EPI>
-__global__ __launch_bounds__(GT) void gemm_kernel(int M, int N, int K, const float* __restrict__ A,
-                                                 int lda, const float* __restrict__ B, int ldb,
+__global__ __launch_bounds__(GT) void gemm_kernel(int M, int N, int K, int kc,
+                                                 const float* __restrict__ A, int lda,
+                                                 const float* __restrict__ B, int ldb,
                                                  float* __restrict__ C, int ldc,
                                                  const float* __restrict__ bias,
                                                  const float* __restrict__ mask, int ldm,
@@ -48,55 +51,60 @@ __global__ __launch_bounds__(GT) void gemm_kernel(int M, int N, int K, const flo
   __shared__ unsigned short Bs[BK][BN + 4];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  const int kbeg = blockIdx.z * kc;
+  const int kend = min(K, kbeg + kc);
+  C += (int64_t)blockIdx.z * M * N;
   const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
   v4f acc[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
-  for (int k0 = 0; k0 < K; k0 += BK) {
-    // A tile 64 x 16: 1024 elements, 4 per thread
+  for (int k0 = kbeg; k0 < kend; k0 += BK) {
+    // A tile 64 x 32 and B tile 32 x 64: 2048 elements each, 8 per thread
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < 8; ++q) {
       const int e = t + q * GT;
       int r, c;
       if (TA) { c = e / BM; r = e % BM; } else { r = e / BK; c = e % BK; }
       const int gm = m0 + r, gk = k0 + c;
       float v = 0.f;
-      if (gm < M && gk < K) v = TA ? A[(int64_t)gk * lda + gm] : A[(int64_t)gm * lda + gk];
+      if (gm < M && gk < kend) v = TA ? A[(int64_t)gk * lda + gm] : A[(int64_t)gm * lda + gk];
       As[r][c] = f2bf(v);
     }
-    // B tile 16 x 64
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < 8; ++q) {
       const int e = t + q * GT;
       int r, c;
       if (TB) { c = e / BK; r = e % BK; } else { r = e / BN; c = e % BN; }
       const int gk = k0 + r, gn = n0 + c;
       float v = 0.f;
-      if (gk < K && gn < N) v = TB ? B[(int64_t)gn * ldb + gk] : B[(int64_t)gk * ldb + gn];
+      if (gk < kend && gn < N) v = TB ? B[(int64_t)gn * ldb + gk] : B[(int64_t)gk * ldb + gn];
       Bs[r][c] = f2bf(v);
     }
     __syncthreads();
-    const int kq = (lane >> 4) * 4;
-    v4s af[2], bf[2];
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      const int row = wm + i * 16 + (lane & 15);
+    for (int kk = 0; kk < BK; kk += 16) {
+      const int kq = kk + (lane >> 4) * 4;
+      v4s af[2], bf[2];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) af[i][j] = (short)As[row][kq + j];
+      for (int i = 0; i < 2; ++i) {
+        const int row = wm + i * 16 + (lane & 15);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) af[i][j] = (short)As[row][kq + j];
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const int col = wn + i * 16 + (lane & 15);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) bf[i][j] = (short)Bs[kq + j][col];
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[i], bf[j], acc[i][j], 0, 0, 0);
     }
-#pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      const int col = wn + i * 16 + (lane & 15);
-#pragma unroll
-      for (int j = 0; j < 4; ++j) bf[i][j] = (short)Bs[kq + j][col];
-    }
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int j = 0; j < 2; ++j)
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[i], bf[j], acc[i][j], 0, 0, 0);
     __syncthreads();
   }
 #pragma unroll
@@ -117,6 +125,16 @@ __global__ __launch_bounds__(GT) void gemm_kernel(int M, int N, int K, const flo
         }
       }
     }
+}
+
+// out[i] = sum_{z < nz} ws[z*n + i], z in order (split-K reduction).
+__global__ void splitk_sum_kernel(int64_t n, int nz, const float* __restrict__ ws,
+                                  float* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float s = 0.f;
+  for (int z = 0; z < nz; ++z) s += ws[(int64_t)z * n + i];
+  out[i] = s;
 }
 
 // Loss on normalised outputs: with yh the network's raw output and
@@ -151,23 +169,42 @@ __global__ void finish_loss_kernel(int nb, const float* part, float scale, float
   }
 }
 
-// Per-column mean and standard deviation of a [rows][cols] array, FP64
-// accumulation, rows in order; sd is floored at sd_min.
-__global__ void colstats_kernel(int64_t rows, int cols, const float* a, float sd_min, float* mu,
-                                float* sd) {
+// Per-column statistics of a [rows][cols] array in two deterministic
+// stages.  colpart: part[k][c] = sum over the rows of chunk k, in order, of
+// (a[r][c] - shift[c])^pw (pw = 1 or 2, shift = 0 when NULL), in FP64.
+__global__ void colpart_kernel(int64_t rows, int cols, int64_t chunk, const float* __restrict__ a,
+                               const double* __restrict__ shift, int pw,
+                               double* __restrict__ part) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= cols) return;
+  const int64_t r0 = (int64_t)blockIdx.y * chunk;
+  const int64_t r1 = r0 + chunk < rows ? r0 + chunk : rows;
+  const double sh = shift ? shift[c] : 0.0;
+  double s = 0.0;
+  for (int64_t r = r0; r < r1; ++r) {
+    const double d = (double)a[r * cols + c] - sh;
+    s += pw == 1 ? d : d * d;
+  }
+  part[(int64_t)blockIdx.y * cols + c] = s;
+}
+
+// Sums the chunk partials in chunk order.  stage 0: mean (kept in FP64 as
+// the shift of the second stage); stage 1: standard deviation, floored.
+__global__ void colfinish_kernel(int cols, int nk, int64_t rows, const double* __restrict__ part,
+                                 int stage, double* __restrict__ mean_d, float* __restrict__ mu,
+                                 float* __restrict__ sd, float sd_min) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= cols) return;
   double s = 0.0;
-  for (int64_t r = 0; r < rows; ++r) s += (double)a[r * cols + c];
-  const double m = s / (double)rows;
-  double q = 0.0;
-  for (int64_t r = 0; r < rows; ++r) {
-    const double d = (double)a[r * cols + c] - m;
-    q += d * d;
+  for (int k = 0; k < nk; ++k) s += part[(int64_t)k * cols + c];
+  if (stage == 0) {
+    const double m = s / (double)rows;
+    mean_d[c] = m;
+    mu[c] = (float)m;
+  } else {
+    const double v = sqrt(s / (double)rows);
+    sd[c] = (float)(v > sd_min ? v : sd_min);
   }
-  const double v = sqrt(q / (double)rows);
-  mu[c] = (float)m;
-  sd[c] = (float)(v > sd_min ? v : sd_min);
 }
 
 __global__ void fill_kernel(int n, float v, float* a) {
@@ -175,13 +212,19 @@ __global__ void fill_kernel(int n, float v, float* a) {
   if (i < n) a[i] = v;
 }
 
-// db[c] = sum_r dY[r][c], one thread per column, rows in order.
-__global__ void colsum_kernel(int rows, int cols, const float* dY, float* db) {
+// Bias gradients db[c] = sum_r dY[r][c] in two deterministic stages:
+// colsum_part sums chunks of CS_ROWS rows in order into ws[k][c], and
+// splitk_sum_kernel adds the chunks in order.
+constexpr int CS_ROWS = 32;
+__global__ void colsum_part_kernel(int rows, int cols, const float* __restrict__ dY,
+                                   float* __restrict__ ws) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= cols) return;
+  const int r0 = blockIdx.y * CS_ROWS;
+  const int r1 = r0 + CS_ROWS < rows ? r0 + CS_ROWS : rows;
   float s = 0.f;
-  for (int r = 0; r < rows; ++r) s += dY[(int64_t)r * cols + c];
-  db[c] = s;
+  for (int r = r0; r < r1; ++r) s += dY[(int64_t)r * cols + c];
+  ws[(int64_t)blockIdx.y * cols + c] = s;
 }
 
 // Adam (Kingma and Ba), bias-corrected, on the flat parameter vector.
@@ -208,6 +251,8 @@ struct admm_mlp {
   float *h1 = nullptr, *h2 = nullptr, *y = nullptr, *dy = nullptr, *dh1 = nullptr, *dh2 = nullptr;
   float* part = nullptr;
   float *mu = nullptr, *sd = nullptr;  // fixed output affine y = mu + sd * yhat
+  float* ws = nullptr;                 // split-K partial products
+  float* cs = nullptr;                 // bias-gradient chunk sums
   int64_t step = 0;
   std::vector<void*> allocs;
   ~admm_mlp() {
@@ -228,13 +273,34 @@ admm_status mlp_alloc(admm_mlp* n, float** q, int64_t count) {
   return ADMM_OK;
 }
 
+constexpr int MAX_SPLITS = 32;
+
 template <bool TA, bool TB, int EPI>
 void gemm(int M, int N, int K, const float* A, int lda, const float* B, int ldb, float* C, int ldc,
           const float* bias, const float* mask, int ldm, hipStream_t st,
-          const float* mu = nullptr, const float* sd = nullptr) {
-  dim3 grid((N + BN - 1) / BN, (M + BM - 1) / BM);
-  gemm_kernel<TA, TB, EPI><<<grid, GT, 0, st>>>(M, N, K, A, lda, B, ldb, C, ldc, bias, mask, ldm,
-                                                 mu, sd);
+          const float* mu = nullptr, const float* sd = nullptr, float* ws = nullptr) {
+  const int gm = (M + BM - 1) / BM, gn = (N + BN - 1) / BN;
+  int splits = 1;
+  if (EPI == EPI_PLAIN && ws != nullptr && ldc == N) {
+    // enough workgroups to fill the device, at least 128 of K per split
+    splits = std::max(1, std::min(MAX_SPLITS, std::min((1024 + gm * gn - 1) / (gm * gn), K / 128)));
+  }
+  const int kc = ((K + splits - 1) / splits + BK - 1) / BK * BK;
+  splits = (K + kc - 1) / kc;
+  dim3 grid(gn, gm, splits);
+  float* dst = splits > 1 ? ws : C;
+  gemm_kernel<TA, TB, EPI><<<grid, GT, 0, st>>>(M, N, K, kc, A, lda, B, ldb, dst, ldc, bias, mask,
+                                                 ldm, mu, sd);
+  if (splits > 1) {
+    const int64_t n = (int64_t)M * N;
+    splitk_sum_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(n, splits, ws, C);
+  }
+}
+
+void colsum(int rows, int cols, const float* dY, float* db, float* cs, hipStream_t st) {
+  const int nk = (rows + CS_ROWS - 1) / CS_ROWS;
+  colsum_part_kernel<<<dim3((cols + 255) / 256, nk), 256, 0, st>>>(rows, cols, dY, cs);
+  splitk_sum_kernel<<<(cols + 255) / 256, 256, 0, st>>>(cols, nk, cs, db);
 }
 
 // forward: h1 = relu(x W1^T + b1), h2 = relu(h1 W2^T + b2),
@@ -264,20 +330,20 @@ void backward(admm_mlp* n, const float* x, const float* tg, int batch, float* lo
   float* g = n->g;
   // layer 3
   gemm<true, false, EPI_PLAIN>(n->n_out, n->hid, batch, n->dy, n->n_out, n->h2, n->hid, g + n->oW3,
-                               n->hid, nullptr, nullptr, 0, st);
-  colsum_kernel<<<(n->n_out + 255) / 256, 256, 0, st>>>(batch, n->n_out, n->dy, g + n->ob3);
+                               n->hid, nullptr, nullptr, 0, st, nullptr, nullptr, n->ws);
+  colsum(batch, n->n_out, n->dy, g + n->ob3, n->cs, st);
   gemm<false, false, EPI_MASK>(batch, n->hid, n->n_out, n->dy, n->n_out, n->p + n->oW3, n->hid,
                                n->dh2, n->hid, nullptr, n->h2, n->hid, st);
   // layer 2
   gemm<true, false, EPI_PLAIN>(n->hid, n->hid, batch, n->dh2, n->hid, n->h1, n->hid, g + n->oW2,
-                               n->hid, nullptr, nullptr, 0, st);
-  colsum_kernel<<<(n->hid + 255) / 256, 256, 0, st>>>(batch, n->hid, n->dh2, g + n->ob2);
+                               n->hid, nullptr, nullptr, 0, st, nullptr, nullptr, n->ws);
+  colsum(batch, n->hid, n->dh2, g + n->ob2, n->cs, st);
   gemm<false, false, EPI_MASK>(batch, n->hid, n->hid, n->dh2, n->hid, n->p + n->oW2, n->hid,
                                n->dh1, n->hid, nullptr, n->h1, n->hid, st);
   // layer 1
   gemm<true, false, EPI_PLAIN>(n->hid, n->n_in, batch, n->dh1, n->hid, x, n->n_in, g + n->oW1,
-                               n->n_in, nullptr, nullptr, 0, st);
-  colsum_kernel<<<(n->hid + 255) / 256, 256, 0, st>>>(batch, n->hid, n->dh1, g + n->ob1);
+                               n->n_in, nullptr, nullptr, 0, st, nullptr, nullptr, n->ws);
+  colsum(batch, n->hid, n->dh1, g + n->ob1, n->cs, st);
 }
 
 }  // namespace
@@ -320,6 +386,13 @@ admm_status admm_mlp_create(int32_t n_in, int32_t hidden, int32_t n_out, int32_t
   if ((s = mlp_alloc(n.get(), &n->dh2, B * hidden))) return s;
   if ((s = mlp_alloc(n.get(), &n->part, LOSS_BLOCKS))) return s;
   if ((s = mlp_alloc(n.get(), &n->mu, n_out))) return s;
+  {
+    const int64_t big = std::max<int64_t>((int64_t)n_out * hidden,
+                                          std::max<int64_t>((int64_t)hidden * hidden, (int64_t)hidden * n_in));
+    if ((s = mlp_alloc(n.get(), &n->ws, big * MAX_SPLITS))) return s;
+    const int64_t chunks = (max_batch + CS_ROWS - 1) / CS_ROWS;
+    if ((s = mlp_alloc(n.get(), &n->cs, chunks * std::max(n_out, hidden)))) return s;
+  }
   if ((s = mlp_alloc(n.get(), &n->sd, n_out))) return s;
   fill_kernel<<<(n_out + 255) / 256, 256>>>(n_out, 0.f, n->mu);
   fill_kernel<<<(n_out + 255) / 256, 256>>>(n_out, 1.f, n->sd);
@@ -401,8 +474,24 @@ admm_status admm_mlp_fit_output_scaling(admm_mlp* n, const float* targets, int64
   if (!n || !targets || rows < 1) return admmi::set_err(ADMM_E_ARG, "bad arguments");
   if (!(sd_min > 0.f)) return admmi::set_err(ADMM_E_ARG, "sd_min must be > 0");
   ADMM_HIP(hipSetDevice(n->device));
-  colstats_kernel<<<(n->n_out + 63) / 64, 64, 0, (hipStream_t)stream>>>(rows, n->n_out, targets,
-                                                                        sd_min, n->mu, n->sd);
+  // chunks of at least 256 rows, at most 1024 chunks
+  const int64_t nk = std::min<int64_t>(1024, (rows + 255) / 256);
+  const int64_t chunk = (rows + nk - 1) / nk;
+  const int nkk = (int)((rows + chunk - 1) / chunk);
+  double* tmp = nullptr;
+  ADMM_HIP(hipMalloc((void**)&tmp, ((size_t)nkk + 1) * n->n_out * sizeof(double)));
+  double* mean_d = tmp + (int64_t)nkk * n->n_out;
+  hipStream_t st = (hipStream_t)stream;
+  const dim3 gp((n->n_out + 255) / 256, nkk);
+  const unsigned gf = (n->n_out + 255) / 256;
+  colpart_kernel<<<gp, 256, 0, st>>>(rows, n->n_out, chunk, targets, nullptr, 1, tmp);
+  colfinish_kernel<<<gf, 256, 0, st>>>(n->n_out, nkk, rows, tmp, 0, mean_d, n->mu, n->sd, sd_min);
+  colpart_kernel<<<gp, 256, 0, st>>>(rows, n->n_out, chunk, targets, mean_d, 2, tmp);
+  colfinish_kernel<<<gf, 256, 0, st>>>(n->n_out, nkk, rows, tmp, 1, mean_d, n->mu, n->sd, sd_min);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  hipFree(tmp);
+  if (e != hipSuccess) return admmi::set_err(ADMM_E_HIP, "output scaling: %s", hipGetErrorString(e));
   ADMM_HIP(hipGetLastError());
   return ADMM_OK;
 }
