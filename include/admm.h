@@ -89,6 +89,8 @@ typedef struct {
   int64_t layout_bytes_per_iter; /* index/partial bytes of one iteration */
   int32_t precision;           /* admm_precision */
   int32_t alpha_is_one;        /* 1: m-only state (alpha == 1) */
+  int32_t driver;              /* ADMM_DRIVER_LAUNCHES or ADMM_DRIVER_RESIDENT */
+  int32_t resident_lds_bytes;  /* LDS image of the resident driver (0 if unused) */
 } admm_graph_info;
 
 /* Message for the last failing call on this thread ("" if none). */
@@ -124,8 +126,18 @@ admm_status admm_graph_set_alpha(admm_graph* g, double alpha);
  *  ADMM_OPT_PAIR_ROWS: disks per row of a dense pair tile (16, 32 or 64;
  *  0 = default, 64).  Each tile holds rows x 64 pairs and
  *  is one workgroup of the x-pass; results do not depend on the choice
- *  beyond the order of the z-sums. */
-enum { ADMM_OPT_PAIR_ROWS = 1 };
+ *  beyond the order of the z-sums.
+ *  ADMM_OPT_DRIVER: how admm_run executes the iterations (Alg. 2 loop).
+ *  ADMM_DRIVER_LAUNCHES: one x-pass and one z-pass launch per iteration,
+ *  enqueued back to back.  ADMM_DRIVER_RESIDENT: the whole run in one
+ *  launch of one workgroup that keeps every per-iteration array in LDS;
+ *  only for small graphs (no dense pair tiles, LDS image within the
+ *  device's per-workgroup limit): finalize returns ADMM_E_UNSUPPORTED when
+ *  the graph does not fit.  ADMM_DRIVER_AUTO (default): resident when the
+ *  graph fits and has at most 64 x-pass plus z-pass blocks, else launches.
+ *  The arithmetic of every step is the same in both drivers. */
+enum { ADMM_OPT_PAIR_ROWS = 1, ADMM_OPT_DRIVER = 2 };
+enum { ADMM_DRIVER_AUTO = 0, ADMM_DRIVER_LAUNCHES = 1, ADMM_DRIVER_RESIDENT = 2 };
 admm_status admm_graph_set_option(admm_graph* g, int32_t option, int64_t value);
 
 /* Validate, bucket factors by kind, build the device layout (edge-major
@@ -152,7 +164,8 @@ admm_status admm_run(admm_graph* g, int32_t iters, void* stream);
 /* admm_run with a HIP event pair around every kernel: same results, and
  * the summed device time of the x-passes and of the z-passes in
  * milliseconds.  Synchronises the stream.  For measurement only: the
- * events add a small gap between kernels. */
+ * events add a small gap between kernels.  With the resident driver the
+ * one launch's time is returned as xpass_ms and zpass_ms is 0. */
 admm_status admm_run_profiled(admm_graph* g, int32_t iters, void* stream,
                               double* xpass_ms, double* zpass_ms);
 

@@ -23,7 +23,8 @@ STATUS_NAMES = {0: "OK", 1: "E_ARG", 2: "E_STATE", 3: "E_NUMERIC", 4: "E_HIP",
 KIND = dict(nonoverlap=1, wall=2, radius=3, quad=4, box=5, hinge=6, l2=7,
             lindyn=8, lindyn0=9)
 FP32, FP64 = 0, 1
-OPT_PAIR_ROWS = 1
+OPT_PAIR_ROWS, OPT_DRIVER = 1, 2
+DRIVER_AUTO, DRIVER_LAUNCHES, DRIVER_RESIDENT = 0, 1, 2
 
 
 class AdmmError(RuntimeError):
@@ -37,7 +38,8 @@ class GraphInfo(ctypes.Structure):
         "n_vars", "n_scalars", "n_factors", "n_edges", "n_slots", "n_buckets",
         "n_pair_tiles", "n_contributions", "state_bytes",
         "algo_bytes_per_iter", "layout_bytes_per_iter")] + [
-        ("precision", ctypes.c_int32), ("alpha_is_one", ctypes.c_int32)]
+        ("precision", ctypes.c_int32), ("alpha_is_one", ctypes.c_int32),
+        ("driver", ctypes.c_int32), ("resident_lds_bytes", ctypes.c_int32)]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}
@@ -210,7 +212,7 @@ class Graph:
     @classmethod
     def from_problem(cls, problem, precision: int = FP32, device: Optional[int] = 0,
                      rho: Optional[float] = None, alpha: Optional[float] = None,
-                     pair_rows: int = 0):
+                     pair_rows: int = 0, driver: int = DRIVER_AUTO):
         """Build from an object with var_dims, groups (kind, var_ids, params,
         shared), rho, alpha and z0.  device=None skips finalize."""
         g = cls(problem.var_dims, precision)
@@ -220,6 +222,8 @@ class Graph:
         g.set_alpha(problem.alpha if alpha is None else alpha)
         if pair_rows:
             g.set_option(OPT_PAIR_ROWS, pair_rows)
+        if driver != DRIVER_AUTO:
+            g.set_option(OPT_DRIVER, driver)
         if device is not None:
             g.finalize(device)
             g.set_state(problem.z0)

@@ -49,19 +49,24 @@ struct Plan {
   std::vector<int32_t> idx;
   std::vector<double> par;
   int64_t n_zc = 0, n_m = 0;    // contribution buffer and m-region element counts
-  std::vector<int32_t> var_w, var_l;
-  std::vector<int64_t> rng_w, rng_l;
-  std::vector<double> deg_w, deg_l;
+  std::vector<int32_t> var_b, var_w, var_l;   // z lists: long, medium, short
+  std::vector<int64_t> rng_b, rng_w, rng_l;
+  std::vector<double> deg_b, deg_w, deg_l;
   std::vector<int64_t> upos;    // user slot -> pool position of m
   std::vector<int32_t> uz;      // user slot -> z index
   int64_t xblocks = 0;
   int64_t algo_bytes = 0, layout_bytes = 0;  // per iteration, in T units x sizeof later
   int64_t algo_elems = 0, layout_idx_bytes = 0, layout_elems = 0;
   int64_t n_pair_tiles = 0;
+  bool no_tiles = false;        // input: build no dense pair tiles
+  bool resident = false;        // output of finalize: resident driver chosen
 };
 
 struct EngineBase {
   virtual ~EngineBase() {}
+  // Whether the resident driver can run this plan on the device (LDS image
+  // plus the kernel's static LDS within the per-workgroup limit).
+  virtual admm_status resident_check(const Plan& p, int64_t nz, bool alpha1) = 0;
   virtual admm_status upload(const Plan& p, const std::vector<double>& z0, double rho,
                              double alpha) = 0;
   virtual admm_status set_state(const double* z, const double* u, hipStream_t s) = 0;
@@ -83,6 +88,7 @@ struct admm_graph {
   std::vector<Group> groups;
   double rho = 1.0, alpha = 1.0;
   int32_t pair_rows = 0;  // rows per dense pair tile (0: chosen at finalize)
+  int32_t driver = ADMM_DRIVER_AUTO;
   int64_t n_factors = 0, n_edges = 0, n_slots = 0;
   int state = 0;  // 0 building, 1 validated (no device), 2 ready
   int device = -1;
@@ -233,8 +239,9 @@ bool hinge_uniform(const Group& gr) {
 }
 
 // Build the device layout.  Validation errors return non-OK.
-admm_status build_plan(admm_graph& g, Plan& P) {
+admm_status build_plan(admm_graph& g, Plan& P, bool no_tiles) {
   P = Plan();
+  P.no_tiles = no_tiles;
   // Every contribution to a z scalar, in emission order: z index and the
   // index-buffer slot that will receive its position in the z-major buffer.
   struct Emit { int64_t z; int64_t key; };
@@ -272,7 +279,8 @@ admm_status build_plan(admm_graph& g, Plan& P) {
     std::vector<int32_t> ezc, ezr, fe1, fe2;
     const bool separable = gr.kind == KD_RADIUS || gr.kind == KD_QUAD || gr.kind == KD_BOX ||
                            gr.kind == KD_L2;
-    if (gr.kind == KD_NONOVERLAP && detect_complete_pairs(g, gr, ezc, ezr, fe1, fe2)) {
+    if (gr.kind == KD_NONOVERLAP && !P.no_tiles &&
+        detect_complete_pairs(g, gr, ezc, ezr, fe1, fe2)) {
       // ---------------- dense pair tiles ----------------
       b.mode = BM_PAIR;
       b.E = (int32_t)ezc.size();
@@ -568,7 +576,12 @@ admm_status build_plan(admm_graph& g, Plan& P) {
     return admmi::set_err(ADMM_E_UNSUPPORTED, "more than 2^31 pool elements");
   for (int64_t zi = 0; zi < g.nz; ++zi) {
     const int64_t len = cnt[zi + 1] - cnt[zi];
-    if (len > LANE_MAX) {
+    if (len > ZB_MIN) {
+      P.var_b.push_back((int32_t)zi);
+      P.rng_b.push_back(cnt[zi]);
+      P.rng_b.push_back(cnt[zi + 1]);
+      P.deg_b.push_back((double)deg[zi]);
+    } else if (len > LANE_MAX) {
       P.var_w.push_back((int32_t)zi);
       P.rng_w.push_back(cnt[zi]);
       P.rng_w.push_back(cnt[zi + 1]);
@@ -586,6 +599,26 @@ admm_status build_plan(admm_graph& g, Plan& P) {
   return ADMM_OK;
 }
 
+int64_t zpass_blocks(const Plan& P) {
+  return (int64_t)P.var_b.size() + ((int64_t)P.var_w.size() + ZPB - 1) / ZPB +
+         ((int64_t)P.var_l.size() + NT - 1) / NT;
+}
+
+// Bytes of the resident driver's LDS image: every region rounded up to 16 B,
+// in the order resident_layout assigns them.
+int64_t resident_image_bytes(const Plan& P, int64_t nz, int64_t es) {
+  auto r16 = [](int64_t b) { return (b + 15) / 16 * 16; };
+  int64_t b = r16((P.n_zc + 2 * P.n_m) * es) + 2 * r16(nz * es) + r16((int64_t)P.par.size() * es) +
+              r16((int64_t)P.idx.size() * 4);
+  b += r16((int64_t)P.var_b.size() * 4) + r16((int64_t)P.rng_b.size() * 8) + r16((int64_t)P.deg_b.size() * es);
+  b += r16((int64_t)P.var_w.size() * 4) + r16((int64_t)P.rng_w.size() * 8) + r16((int64_t)P.deg_w.size() * es);
+  b += r16((int64_t)P.var_l.size() * 4) + r16((int64_t)P.rng_l.size() * 8) + r16((int64_t)P.deg_l.size() * es);
+  return b;
+}
+
+constexpr int64_t RES_LDS_BYTES = 96 * 1024;   // image limit of the resident driver
+constexpr int64_t RES_AUTO_MAX_BLOCKS = 64;    // auto: resident up to this many pass blocks
+
 // ---------------------------------------------------------------------------
 // Device engine for one working precision.
 // ---------------------------------------------------------------------------
@@ -597,6 +630,13 @@ struct Engine : EngineBase {
   int nb = 0;
   int fs = FS_ALL;  // x-pass feature set
   int64_t xblocks = 0, zblocks = 0, nb_w = 0, n_w = 0, n_l = 0, n_slots = 0, nz = 0, xdelta = 0;
+  int64_t n_b = 0;
+  int32_t *var_b = nullptr;
+  int64_t* rng_b = nullptr;
+  T* deg_b = nullptr;
+  bool resident = false;
+  ResArgs<T> ra{};
+  size_t res_lds = 0;
   T* pool = nullptr;
   T* par = nullptr;
   int32_t* idx = nullptr;
@@ -643,6 +683,71 @@ struct Engine : EngineBase {
     return put(p, t);
   }
 
+  template <bool A1>
+  static const void* resident_fn() {
+    return reinterpret_cast<const void*>(&resident_kernel<T, A1>);
+  }
+
+  admm_status resident_check(const Plan& P, int64_t nz_, bool a1) override {
+    const int64_t bytes = resident_image_bytes(P, nz_, (int64_t)sizeof(T));
+    hipFuncAttributes fa;
+    ADMM_HIP(hipFuncGetAttributes(&fa, a1 ? resident_fn<true>() : resident_fn<false>()));
+    int maxsh = 0;
+    ADMM_HIP(hipDeviceGetAttribute(&maxsh, hipDeviceAttributeMaxSharedMemoryPerBlock, device));
+    if ((int64_t)fa.sharedSizeBytes + bytes > (int64_t)maxsh)
+      return admmi::set_err(ADMM_E_UNSUPPORTED,
+                            "resident driver: LDS image %lld B + static %zu B exceeds %d B",
+                            (long long)bytes, (size_t)fa.sharedSizeBytes, maxsh);
+    if (bytes > 64 * 1024) {
+      ADMM_HIP(hipFuncSetAttribute(a1 ? resident_fn<true>() : resident_fn<false>(),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+    }
+    return ADMM_OK;
+  }
+
+  // Region table and LDS offsets of the resident driver (same order and
+  // rounding as resident_image_bytes).
+  void resident_layout() {
+    ResArgs<T>& r = ra;
+    r = ResArgs<T>{};
+    int32_t off = 0;
+    auto add = [&](const void* src, void* back, int64_t bytes) {
+      const int32_t o = off;
+      if (bytes > 0) {
+        ResRegion& q = r.reg[r.nreg++];
+        q.src = src;
+        q.back = back;
+        q.off = o;
+        q.words = (int32_t)(bytes / 4);
+      }
+      off += (int32_t)((bytes + 15) / 16 * 16);
+      return o;
+    };
+    const int64_t es = (int64_t)sizeof(T);
+    r.o_pool = add(pool, pool, pool_n * es);
+    r.o_z0 = add(z[0], nullptr, nz * es);
+    r.o_z1 = add(z[1], nullptr, nz * es);
+    r.o_par = add(par, nullptr, par_n * es);
+    r.o_idx = add(idx, nullptr, idx_n * 4);
+    r.o_var_b = add(var_b, nullptr, n_b * 4);
+    r.o_rng_b = add(rng_b, nullptr, n_b * 16);
+    r.o_deg_b = add(deg_b, nullptr, n_b * es);
+    r.o_var_w = add(var_w, nullptr, n_w * 4);
+    r.o_rng_w = add(rng_w, nullptr, n_w * 16);
+    r.o_deg_w = add(deg_w, nullptr, n_w * es);
+    r.o_var_l = add(var_l, nullptr, n_l * 4);
+    r.o_rng_l = add(rng_l, nullptr, n_l * 16);
+    r.o_deg_l = add(deg_l, nullptr, n_l * es);
+    r.xblocks = (int32_t)xblocks;
+    r.zblocks = (int32_t)zblocks;
+    r.z_words = (int32_t)(nz * es / 4);
+    r.z_back[0] = z[0];
+    r.z_back[1] = z[1];
+    res_lds = (size_t)off;
+  }
+
+  int64_t pool_n = 0, par_n = 0, idx_n = 0;
+
   admm_status upload(const Plan& P, const std::vector<double>& z0, double rho,
                      double alpha_) override {
     alpha1 = (alpha_ == 1.0);
@@ -660,15 +765,19 @@ struct Engine : EngineBase {
       }
       fs = ((need & ~FS_PAIR) == 0) ? FS_PAIR : ((need & ~FS_HINGE) == 0) ? FS_HINGE : FS_ALL;
     }
+    n_b = (int64_t)P.var_b.size();
     n_w = (int64_t)P.var_w.size();
     n_l = (int64_t)P.var_l.size();
     nb_w = (n_w + ZPB - 1) / ZPB;
-    zblocks = nb_w + (n_l + NT - 1) / NT;
+    zblocks = zpass_blocks(P);
+    resident = P.resident;
     n_slots = (int64_t)P.upos.size();
     nz = (int64_t)z0.size();
     xdelta = P.n_m;
     admm_status s;
-    const int64_t pool_n = P.n_zc + 2 * P.n_m;
+    pool_n = P.n_zc + 2 * P.n_m;
+    par_n = (int64_t)P.par.size();
+    idx_n = (int64_t)P.idx.size();
     if ((s = alloc(&pool, pool_n))) return s;
     ADMM_HIP(hipMemset(pool, 0, (size_t)std::max<int64_t>(pool_n, 1) * sizeof(T)));
     if ((s = put_conv(&par, P.par))) return s;
@@ -676,6 +785,9 @@ struct Engine : EngineBase {
     if ((s = put(&bt, P.bt))) return s;
     if ((s = alloc(&z[0], nz))) return s;
     if ((s = alloc(&z[1], nz))) return s;
+    if ((s = put(&var_b, P.var_b))) return s;
+    if ((s = put(&rng_b, P.rng_b))) return s;
+    if ((s = put_conv(&deg_b, P.deg_b))) return s;
     if ((s = put(&var_w, P.var_w))) return s;
     if ((s = put(&var_l, P.var_l))) return s;
     if ((s = put(&rng_w, P.rng_w))) return s;
@@ -688,6 +800,7 @@ struct Engine : EngineBase {
     if ((s = alloc(&bmz, zblocks))) return s;
     io_n = std::max(n_slots, nz);
     if ((s = alloc(&io, io_n))) return s;
+    if (resident) resident_layout();
     return set_state(z0.data(), nullptr, nullptr);
   }
 
@@ -745,9 +858,13 @@ struct Engine : EngineBase {
     else launch_x_fs<A1, FS_ALL>(mode, st, e0, e1);
   }
 
-  void launch_z(int check, hipStream_t st, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
+  ZArgs<T> zargs(int check) const {
     ZArgs<T> a;
     a.pool = pool;
+    a.var_b = var_b;
+    a.rng_b = rng_b;
+    a.deg_b = deg_b;
+    a.n_b = (int32_t)n_b;
     a.var_w = var_w;
     a.rng_w = rng_w;
     a.deg_w = deg_w;
@@ -761,14 +878,42 @@ struct Engine : EngineBase {
     a.zout = z[zc ^ 1];
     a.blockmax = bmz;
     a.check = check;
+    return a;
+  }
+
+  void launch_z(int check, hipStream_t st, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
+    ZArgs<T> a = zargs(check);
     if (zblocks)
       hipExtLaunchKernelGGL((zpass_kernel<T>), dim3((unsigned)zblocks), dim3(NT), 0, st, e0, e1, 0, a);
     zc ^= 1;
   }
 
+  // The whole run in one launch of one workgroup (resident driver).
+  void launch_resident(int32_t iters, hipStream_t st, hipEvent_t e0 = nullptr,
+                       hipEvent_t e1 = nullptr) {
+    ResArgs<T> r = ra;
+    r.zc = zc;
+    r.iters = iters;
+    const XArgs<T> xa = xargs();
+    const ZArgs<T> za = zargs(0);
+    if (alpha1)
+      hipExtLaunchKernelGGL((resident_kernel<T, true>), dim3(1), dim3(NT), res_lds, st, e0, e1, 0,
+                            xa, za, r);
+    else
+      hipExtLaunchKernelGGL((resident_kernel<T, false>), dim3(1), dim3(NT), res_lds, st, e0, e1, 0,
+                            xa, za, r);
+    if (iters & 1) zc ^= 1;
+  }
+
   admm_status run(int32_t iters, hipStream_t st) override {
     if (iters <= 0) return ADMM_OK;
     ADMM_HIP(hipSetDevice(device));
+    if (resident) {
+      launch_resident(iters, st);
+      ADMM_HIP(hipGetLastError());
+      have_resid = true;
+      return ADMM_OK;
+    }
     for (int32_t k = 0; k < iters; ++k) {
       const bool last = (k == iters - 1);
       if (xblocks) {
@@ -793,6 +938,22 @@ struct Engine : EngineBase {
     *z_ms = 0.0;
     if (iters <= 0) return ADMM_OK;
     ADMM_HIP(hipSetDevice(device));
+    if (resident) {
+      hipEvent_t e0, e1;
+      ADMM_HIP(hipEventCreate(&e0));
+      ADMM_HIP(hipEventCreate(&e1));
+      launch_resident(iters, st, e0, e1);
+      hipError_t e = hipGetLastError();
+      if (e == hipSuccess) e = hipStreamSynchronize(st);
+      float ms = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      hipEventDestroy(e0);
+      hipEventDestroy(e1);
+      if (e != hipSuccess) return admmi::set_err(ADMM_E_HIP, "profiled run: %s", hipGetErrorString(e));
+      *x_ms = ms;
+      have_resid = true;
+      return ADMM_OK;
+    }
     std::vector<hipEvent_t> ev(4 * (size_t)iters);
     for (auto& e : ev) ADMM_HIP(hipEventCreate(&e));
     admm_status rc = ADMM_OK;
@@ -988,6 +1149,11 @@ admm_status admm_graph_set_option(admm_graph* g, int32_t option, int64_t value) 
         return admmi::set_err(ADMM_E_ARG, "pair tile rows must be 0, 16, 32 or 64");
       g->pair_rows = (int32_t)value;
       return ADMM_OK;
+    case ADMM_OPT_DRIVER:
+      if (value != ADMM_DRIVER_AUTO && value != ADMM_DRIVER_LAUNCHES && value != ADMM_DRIVER_RESIDENT)
+        return admmi::set_err(ADMM_E_ARG, "driver must be 0 (auto), 1 (launches) or 2 (resident)");
+      g->driver = (int32_t)value;
+      return ADMM_OK;
     default:
       return admmi::set_err(ADMM_E_ARG, "unknown option %d", option);
   }
@@ -997,7 +1163,26 @@ admm_status admm_graph_finalize(admm_graph* g, int32_t device) {
   admmi::clear_err();
   if (admm_status s = check_graph(g)) return s;
   if (g->state == 2) return admmi::set_err(ADMM_E_STATE, "graph already finalized");
-  if (admm_status s = build_plan(*g, g->plan)) return s;
+  const int64_t es_ = g->precision == ADMM_FP64 ? 8 : 4;
+  // Resident candidates: the m and x regions alone must fit the LDS image.
+  bool want_res = g->driver != ADMM_DRIVER_LAUNCHES && g->n_slots * 2 * es_ <= RES_LDS_BYTES;
+  if (g->driver == ADMM_DRIVER_RESIDENT && !want_res)
+    return admmi::set_err(ADMM_E_UNSUPPORTED, "resident driver: %lld slots do not fit in LDS",
+                          (long long)g->n_slots);
+  if (admm_status s = build_plan(*g, g->plan, want_res)) return s;
+  if (want_res) {
+    const int64_t bytes = resident_image_bytes(g->plan, g->nz, es_);
+    const int64_t blocks = g->plan.xblocks + zpass_blocks(g->plan);
+    bool ok = bytes <= RES_LDS_BYTES;
+    if (g->driver == ADMM_DRIVER_RESIDENT && !ok)
+      return admmi::set_err(ADMM_E_UNSUPPORTED, "resident driver: LDS image of %lld B exceeds %lld B",
+                            (long long)bytes, (long long)RES_LDS_BYTES);
+    if (g->driver == ADMM_DRIVER_AUTO && blocks > RES_AUTO_MAX_BLOCKS) ok = false;
+    if (!ok) {
+      if (admm_status s = build_plan(*g, g->plan, false)) return s;
+    }
+    g->plan.resident = ok;
+  }
   const Plan& P = g->plan;
   const int64_t es = g->precision == ADMM_FP64 ? 8 : 4;
   admm_graph_info& I = g->info;
@@ -1016,6 +1201,8 @@ admm_status admm_graph_finalize(admm_graph* g, int32_t device) {
   // per-factor prox data; layout: indices, partial sums and their reads.
   I.algo_bytes_per_iter = P.algo_elems * es * (g->alpha == 1.0 ? 1 : 2);
   I.layout_bytes_per_iter = P.layout_elems * es + P.layout_idx_bytes;
+  I.driver = P.resident ? ADMM_DRIVER_RESIDENT : ADMM_DRIVER_LAUNCHES;
+  I.resident_lds_bytes = P.resident ? (int32_t)resident_image_bytes(P, g->nz, es) : 0;
   if (admm_status s = admmi::probe_device(device)) {
     g->state = 1;
     return s;
@@ -1030,6 +1217,15 @@ admm_status admm_graph_finalize(admm_graph* g, int32_t device) {
     auto* e = new Engine<float>();
     e->device = device;
     eng.reset(e);
+  }
+  if (g->plan.resident) {
+    if (admm_status s = eng->resident_check(P, g->nz, g->alpha == 1.0)) {
+      if (g->driver == ADMM_DRIVER_RESIDENT) return s;
+      admmi::clear_err();
+      g->plan.resident = false;  // auto: the same plan runs with launches
+      I.driver = ADMM_DRIVER_LAUNCHES;
+      I.resident_lds_bytes = 0;
+    }
   }
   std::vector<double> z0(g->nz, 0.0);
   if (admm_status s = eng->upload(P, z0, g->rho, g->alpha)) return s;

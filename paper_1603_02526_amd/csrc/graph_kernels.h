@@ -27,6 +27,7 @@ constexpr int PR = PB * PB / NT;     // pair rows per thread
 constexpr int MAXN = 16;             // lindyn state dim limit (general path)
 constexpr int MAXM = 8;              // lindyn input dim limit (general path)
 constexpr int LANE_MAX = 4;          // z-lists up to this length: one lane
+constexpr int ZB_MIN = 128;          // z-lists longer than this: one workgroup
 
 enum BucketMode : int32_t {
   BM_PAIR = 1,        // complete pairwise non-overlap, dense 64x64 tiles
@@ -73,7 +74,11 @@ struct XArgs {
 template <typename T>
 struct ZArgs {
   const T* pool;
-  const int32_t* var_w;
+  const int32_t* var_b;   // lists of more than ZB_MIN contributions: one block each
+  const int64_t* rng_b;
+  const T* deg_b;
+  int32_t n_b;
+  const int32_t* var_w;   // lists of LANE_MAX+1 .. ZB_MIN: one 16-lane row each
   const int64_t* rng_w;
   const T* deg_w;
   int64_t n_w;
@@ -95,7 +100,8 @@ __device__ __forceinline__ T tmax(T a, T b) { return a > b ? a : b; }
 template <typename T>
 __device__ __forceinline__ T tmin(T a, T b) { return a < b ? a : b; }
 
-// Block-wide max of non-negative values, stored by thread 0.
+// Block-wide max of non-negative values, stored by thread 0 at *out (the
+// caller points out at its block's slot).
 template <typename T>
 __device__ __forceinline__ void block_max_store(T v, T* out) {
   __shared__ T red[NT / 64];
@@ -106,7 +112,7 @@ __device__ __forceinline__ void block_max_store(T v, T* out) {
     T mx = red[0];
 #pragma unroll
     for (int i = 1; i < NT / 64; ++i) mx = tmax(mx, red[i]);
-    out[blockIdx.x] = mx;
+    out[0] = mx;
   }
 }
 
@@ -616,9 +622,10 @@ constexpr int FS_PAIR = FT_PAIR | FT_GEN;
 constexpr int FS_HINGE = FT_UHINGE | FT_GEN;
 constexpr int FS_ALL = FT_PAIR | FT_UHINGE | FT_GEN | FT_WIDE;
 
+// One x-pass workgroup's work; blk indexes the x-pass blocks of all buckets.
 template <typename T, bool A1, int MODE, int FS>
-__global__ __launch_bounds__(NT) void xpass_kernel(XArgs<T> a) {
-  const int blk = blockIdx.x;
+__device__ __forceinline__ void xpass_block(XArgs<T> a, int blk) {
+  a.blockmax += blk;
   int bi = 0;
   while (bi + 1 < a.nb && blk >= a.bt[bi].blk1) ++bi;
   const BucketDesc b = a.bt[bi];
@@ -651,18 +658,42 @@ __global__ __launch_bounds__(NT) void xpass_kernel(XArgs<T> a) {
   }
 }
 
-// z_b = sum(contributions) / deg(b).  Blocks [0, nb_w): sixteen lists of
-// more than LANE_MAX contributions per block, one 16-lane row each (lanes
-// stride the list, then a fixed DPP tree); remaining blocks: one short list
-// per lane, summed in order.
-constexpr int ZSEG = 16;                  // lanes per long list
-constexpr int ZPB = NT / ZSEG;            // long lists per block
+template <typename T, bool A1, int MODE, int FS>
+__global__ __launch_bounds__(NT) void xpass_kernel(XArgs<T> a) {
+  xpass_block<T, A1, MODE, FS>(a, blockIdx.x);
+}
+
+// z_b = sum(contributions) / deg(b), contributions read from one contiguous
+// range per scalar.  Blocks [0, n_b): one long list each (lanes stride the
+// list, then wavefront DPP trees and the four wavefront sums in order);
+// the next nb_w blocks: sixteen lists each, one 16-lane row per list;
+// remaining blocks: one short list per lane, summed in order.
+constexpr int ZSEG = 16;                  // lanes per medium list
+constexpr int ZPB = NT / ZSEG;            // medium lists per block
 template <typename T>
-__global__ __launch_bounds__(NT) void zpass_kernel(ZArgs<T> a) {
+__device__ __forceinline__ void zpass_block(ZArgs<T> a, int blk) {
+  __shared__ T zred[NT / 64];
+  a.blockmax += blk;
   T dmax = T(0);
-  if ((int)blockIdx.x < a.nb_w) {
+  if (blk < a.n_b) {
+    const int64_t o1 = a.rng_b[2 * blk + 1];
+    T s = T(0);
+    for (int64_t j = a.rng_b[2 * blk] + threadIdx.x; j < o1; j += NT) s += a.pool[j];
+    s = admmi::wave_sum(s);
+    if ((threadIdx.x & 63) == 0) zred[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      T t = zred[0];
+#pragma unroll
+      for (int q = 1; q < NT / 64; ++q) t += zred[q];
+      const int zi = a.var_b[blk];
+      const T zn = t / a.deg_b[blk];
+      a.zout[zi] = zn;
+      if (a.check) dmax = tabs(zn - a.zin[zi]);
+    }
+  } else if (blk < a.n_b + a.nb_w) {
     const int sl = threadIdx.x & (ZSEG - 1);
-    const int64_t k = (int64_t)blockIdx.x * ZPB + (threadIdx.x / ZSEG);
+    const int64_t k = (int64_t)(blk - a.n_b) * ZPB + (threadIdx.x / ZSEG);
     const bool ok = k < a.n_w;
     T s = T(0);
     if (ok) {
@@ -677,7 +708,7 @@ __global__ __launch_bounds__(NT) void zpass_kernel(ZArgs<T> a) {
       if (a.check) dmax = tabs(zn - a.zin[zi]);
     }
   } else {
-    const int64_t k = (int64_t)(blockIdx.x - a.nb_w) * NT + threadIdx.x;
+    const int64_t k = (int64_t)(blk - a.n_b - a.nb_w) * NT + threadIdx.x;
     if (k < a.n_l) {
       const int zi = a.var_l[k];
       const int64_t o0 = a.rng_l[2 * k], o1 = a.rng_l[2 * k + 1];
@@ -692,6 +723,99 @@ __global__ __launch_bounds__(NT) void zpass_kernel(ZArgs<T> a) {
     }
   }
   if (a.check) block_max_store(dmax, a.blockmax);
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT) void zpass_kernel(ZArgs<T> a) {
+  zpass_block<T>(a, blockIdx.x);
+}
+
+// ---------------------------------------------------------------------------
+// Resident driver for graphs whose whole state fits in one workgroup's LDS:
+// every iteration of a run in one launch of one workgroup.  The regions the
+// passes touch (pool, z ping-pong, parameters, indices, contribution lists)
+// are copied into LDS at the start, the x-pass and z-pass blocks run one
+// after another with workgroup barriers in between (the order that separate
+// launches would impose), and the pool and the final z are copied back.
+// Bucket descriptors stay in global memory.  Pair tiles are not used here.
+// ---------------------------------------------------------------------------
+constexpr int RES_MAX_REG = 16;
+constexpr int FS_RES = FT_UHINGE | FT_GEN | FT_WIDE;
+
+struct ResRegion {
+  const void* src;  // global source
+  void* back;       // global destination of the copy-back (NULL: none)
+  int32_t off;      // byte offset in LDS (multiple of 16)
+  int32_t words;    // 4-byte words
+};
+
+template <typename T>
+struct ResArgs {
+  ResRegion reg[RES_MAX_REG];
+  int32_t nreg;
+  int32_t o_pool, o_par, o_idx, o_z0, o_z1;
+  int32_t o_var_b, o_rng_b, o_deg_b, o_var_w, o_rng_w, o_deg_w, o_var_l, o_rng_l, o_deg_l;
+  int32_t zc, iters, xblocks, zblocks, z_words;
+  T* z_back[2];     // global z buffers (the final z is copied to z_back[final index])
+};
+
+template <typename T, bool A1>
+__global__ __launch_bounds__(NT) void resident_kernel(XArgs<T> xa, ZArgs<T> za, ResArgs<T> r) {
+  extern __shared__ __align__(16) unsigned char lds_img[];
+  for (int q = 0; q < r.nreg; ++q) {
+    const uint32_t* src = (const uint32_t*)r.reg[q].src;
+    uint32_t* dst = (uint32_t*)(lds_img + r.reg[q].off);
+    for (int i = threadIdx.x; i < r.reg[q].words; i += NT) dst[i] = src[i];
+  }
+  __syncthreads();
+  T* zb[2] = {(T*)(lds_img + r.o_z0), (T*)(lds_img + r.o_z1)};
+  xa.pool = (T*)(lds_img + r.o_pool);
+  xa.par = (const T*)(lds_img + r.o_par);
+  xa.idx = (const int32_t*)(lds_img + r.o_idx);
+  za.pool = xa.pool;
+  za.var_b = (const int32_t*)(lds_img + r.o_var_b);
+  za.rng_b = (const int64_t*)(lds_img + r.o_rng_b);
+  za.deg_b = (const T*)(lds_img + r.o_deg_b);
+  za.var_w = (const int32_t*)(lds_img + r.o_var_w);
+  za.rng_w = (const int64_t*)(lds_img + r.o_rng_w);
+  za.deg_w = (const T*)(lds_img + r.o_deg_w);
+  za.var_l = (const int32_t*)(lds_img + r.o_var_l);
+  za.rng_l = (const int64_t*)(lds_img + r.o_rng_l);
+  za.deg_l = (const T*)(lds_img + r.o_deg_l);
+  int zc = r.zc;
+  for (int k = 0; k < r.iters; ++k) {
+    const bool last = (k == r.iters - 1);
+    xa.z = zb[zc];
+    for (int b = 0; b < r.xblocks; ++b) {
+      if (A1 && last)
+        xpass_block<T, A1, PM_SAVE, FS_RES>(xa, b);
+      else
+        xpass_block<T, A1, PM_NORMAL, FS_RES>(xa, b);
+      __syncthreads();
+    }
+    za.zin = zb[zc];
+    za.zout = zb[zc ^ 1];
+    za.check = last ? 1 : 0;
+    for (int b = 0; b < r.zblocks; ++b) {
+      zpass_block<T>(za, b);
+      __syncthreads();
+    }
+    zc ^= 1;
+  }
+  xa.z = zb[zc];
+  for (int b = 0; b < r.xblocks; ++b) {
+    xpass_block<T, A1, PM_RESID, FS_RES>(xa, b);
+    __syncthreads();
+  }
+  for (int q = 0; q < r.nreg; ++q) {
+    if (!r.reg[q].back) continue;
+    const uint32_t* src = (const uint32_t*)(lds_img + r.reg[q].off);
+    uint32_t* dst = (uint32_t*)r.reg[q].back;
+    for (int i = threadIdx.x; i < r.reg[q].words; i += NT) dst[i] = src[i];
+  }
+  const uint32_t* zs = (const uint32_t*)zb[zc];
+  uint32_t* zd = (uint32_t*)r.z_back[zc];
+  for (int i = threadIdx.x; i < r.z_words; i += NT) zd[i] = zs[i];
 }
 
 // State import: m = u + z_b (x = z_b) for every user slot.

@@ -52,7 +52,7 @@ def _expected_tiles(N, rb):
 @pytest.mark.parametrize("rb", [16, 32, 64])
 def test_packing_layout(name, N, rb):
     p = W.workload(name)
-    g = A.Graph.from_problem(p, device=None, pair_rows=rb)
+    g = A.Graph.from_problem(p, device=None, pair_rows=rb, driver=A.DRIVER_LAUNCHES)
     assert _finalize_cpu(g) in (A.OK, A.E_NO_DEVICE)
     inf = g.info()
     assert inf["n_edges"] == p.n_edges and inf["n_slots"] == p.n_slots
@@ -61,6 +61,39 @@ def test_packing_layout(name, N, rb):
     assert inf["n_pair_tiles"] == _expected_tiles(N, rb)
     # algorithmic bytes: m read + write per slot, plus wall/radius/pair data
     assert inf["algo_bytes_per_iter"] >= 8 * p.n_slots
+
+
+def test_driver_selection():
+    # small graphs: resident in LDS, no pair tiles; forced launches keep tiles
+    p = W.workload("packing_tri10")
+    g = A.Graph.from_problem(p, device=None)
+    assert _finalize_cpu(g) in (A.OK, A.E_NO_DEVICE)
+    inf = g.info()
+    assert inf["driver"] == A.DRIVER_RESIDENT and inf["n_pair_tiles"] == 0
+    # the image holds at least the pool (contributions, m and x) and two z copies
+    assert inf["resident_lds_bytes"] >= 4 * (inf["n_contributions"] + 2 * p.n_slots + 2 * p.n_scalars)
+    assert inf["resident_lds_bytes"] <= 96 * 1024
+    g = A.Graph.from_problem(p, device=None, driver=A.DRIVER_LAUNCHES)
+    assert _finalize_cpu(g) in (A.OK, A.E_NO_DEVICE)
+    inf = g.info()
+    assert inf["driver"] == A.DRIVER_LAUNCHES and inf["n_pair_tiles"] == 1
+    assert inf["resident_lds_bytes"] == 0
+    # large graphs: launches; the resident driver is refused
+    p = W.workload("packing_sq2000")
+    g = A.Graph.from_problem(p, device=None)
+    assert _finalize_cpu(g) in (A.OK, A.E_NO_DEVICE)
+    assert g.info()["driver"] == A.DRIVER_LAUNCHES
+    g = A.Graph.from_problem(p, device=None, driver=A.DRIVER_RESIDENT)
+    assert _finalize_cpu(g) == A.E_UNSUPPORTED
+    # FP64 doubles the image: a graph that fits in FP32 may not in FP64
+    q = W.svm(1500, 4, seed=5)
+    g32 = A.Graph.from_problem(q, device=None)
+    g64 = A.Graph.from_problem(q, precision=A.FP64, device=None)
+    assert _finalize_cpu(g32) in (A.OK, A.E_NO_DEVICE)
+    assert _finalize_cpu(g64) in (A.OK, A.E_NO_DEVICE)
+    i32, i64 = g32.info(), g64.info()
+    if i64["driver"] == A.DRIVER_RESIDENT:
+        assert i64["resident_lds_bytes"] > i32["resident_lds_bytes"]
 
 
 def test_svm_layout():
@@ -110,6 +143,7 @@ def test_validation_errors():
     _expect(A.E_ARG, g.set_rho, -1.0)
     _expect(A.E_ARG, g.set_alpha, 0.0)
     _expect(A.E_ARG, g.set_option, A.OPT_PAIR_ROWS, 48)
+    _expect(A.E_ARG, g.set_option, A.OPT_DRIVER, 3)
     _expect(A.E_ARG, g.set_option, 99, 1)
 
 

@@ -22,8 +22,9 @@ pytestmark = pytest.mark.gpu
 FP32, FP64 = A.FP32, A.FP64
 
 
-def _pair(problem, iters, precision, alpha=None, u0=None, pair_rows=0):
-    g = A.Graph.from_problem(problem, precision=precision, alpha=alpha, pair_rows=pair_rows)
+def _pair(problem, iters, precision, alpha=None, u0=None, pair_rows=0, driver=A.DRIVER_AUTO):
+    g = A.Graph.from_problem(problem, precision=precision, alpha=alpha, pair_rows=pair_rows,
+                             driver=driver)
     o = O.OracleGraph(problem, alpha=alpha)
     if u0 is not None:
         g.set_state(problem.z0, u0)
@@ -66,10 +67,10 @@ def _conditioning(problem, iters, prec, alpha=None, u0=None):
     return rel(b.z, a.z)
 
 
-def _traj(problem, iters, prec, tol, alpha=None, u0=None, pair_rows=0):
+def _traj(problem, iters, prec, tol, alpha=None, u0=None, pair_rows=0, driver=A.DRIVER_AUTO):
     sens = _conditioning(problem, iters, prec, alpha, u0)
     assert sens < tol / 20, f"test case ill-conditioned: oracle self-sensitivity {sens:.2e}"
-    g, o = _pair(problem, iters, prec, alpha=alpha, u0=u0, pair_rows=pair_rows)
+    g, o = _pair(problem, iters, prec, alpha=alpha, u0=u0, pair_rows=pair_rows, driver=driver)
     _check(g, o, tol)
     return g, o
 
@@ -98,10 +99,10 @@ def test_packing_triangle_10_final_objective_fp32():
                                           (130, "triangle", 7), (200, "square", 4)])
 def test_packing_tiles_ragged_fp64(N, shape, seed, rb):
     p = W.packing(N, shape, 0.3 / np.sqrt(N), seed=seed)
-    g, o = _traj(p, 15, FP64, 1e-9, pair_rows=rb)
+    g, o = _traj(p, 15, FP64, 1e-9, pair_rows=rb, driver=A.DRIVER_LAUNCHES)
     assert g.info()["n_pair_tiles"] == len({(i // rb, j // 64) for i in range(N)
                                             for j in range(i + 1, N)})
-    _one_step(p, 40, FP64, 1e-12, pair_rows=rb)
+    _one_step(p, 40, FP64, 1e-12, pair_rows=rb, driver=A.DRIVER_LAUNCHES)
 
 
 @pytest.mark.parametrize("N,seed", [(65, 12), (200, 12)])
@@ -217,12 +218,13 @@ def test_determinism_and_resume():
     assert np.array_equal(a.z(), d.z())
 
 
-def _one_step(problem, warm_iters, prec, tol, alpha=None, pair_rows=0):
+def _one_step(problem, warm_iters, prec, tol, alpha=None, pair_rows=0, driver=A.DRIVER_AUTO):
     """Run the GPU warm_iters iterations, hand its (z, u) to both sides and
     compare one further iteration element by element (no trajectory
     sensitivity involved), then check that the duals around every variable
     sum to zero (Algorithm 2 with u0 = 0 keeps that at any size)."""
-    g = A.Graph.from_problem(problem, precision=prec, alpha=alpha, pair_rows=pair_rows)
+    g = A.Graph.from_problem(problem, precision=prec, alpha=alpha, pair_rows=pair_rows,
+                             driver=driver)
     g.run(warm_iters)
     z, u = g.z(), g.u()
     g.set_state(z, u)
@@ -253,3 +255,80 @@ def test_full_size_packing_2000_fp64_iterates():
     g, o = _pair(p, 3, FP64)
     _check(g, o, 1e-10)
     _one_step(p, 30, FP64, 1e-12)
+
+
+# ---------------------------------------------------------------------------
+# Resident driver: the whole run in one workgroup with the state in LDS.
+# ---------------------------------------------------------------------------
+def _small_cases():
+    inst = W.mpc_batch(1, seed=44)[0]
+    inst.T = 12
+    return {
+        "packing_tri10": W.workload("packing_tri10"),
+        "packing_2": W.packing(2, "square", 0.2, seed=1),
+        "packing_12_general_pairs": W.packing(12, "square", 0.12, seed=2),
+        "svm_300_d3": W.svm(300, 3, seed=311),
+        "mpc_T12": W.mpc_graph(inst),
+    }
+
+
+@pytest.mark.parametrize("name", ["packing_tri10", "packing_2", "svm_300_d3", "mpc_T12"])
+@pytest.mark.parametrize("prec,iters,tol", [(FP64, 60, 1e-9), (FP32, 30, 1e-4)])
+def test_resident_driver_parity(name, prec, iters, tol):
+    p = _small_cases()[name]
+    g, o = _traj(p, iters, prec, tol, driver=A.DRIVER_RESIDENT)
+    inf = g.info()
+    assert inf["driver"] == A.DRIVER_RESIDENT and inf["n_pair_tiles"] == 0
+    assert 0 < inf["resident_lds_bytes"] <= 96 * 1024
+    r, s = g.residuals()
+    ro, so = o.residuals()
+    small = 1e-12 if prec == FP64 else 1e-5
+    assert abs(r - ro) <= 1e-6 * max(ro, 1e-12) + small
+    assert abs(s - so) <= 1e-6 * max(so, 1e-12) + small
+
+
+@pytest.mark.parametrize("alpha", [1.0, 1.5])
+def test_resident_driver_alpha_and_u0_fp64(alpha):
+    p = _small_cases()["packing_12_general_pairs"]
+    u0 = np.random.default_rng(6).standard_normal(p.n_slots) * 0.01
+    g, o = _traj(p, 25, FP64, 1e-9, alpha=alpha, u0=u0, driver=A.DRIVER_RESIDENT)
+    assert g.info()["driver"] == A.DRIVER_RESIDENT
+    _one_step(p, 30, FP64, 1e-12, alpha=alpha, driver=A.DRIVER_RESIDENT)
+
+
+@pytest.mark.parametrize("name", ["svm_300_d3", "mpc_T12"])
+def test_resident_matches_launches(name):
+    """Without pair tiles both drivers run the same plan: same iterates."""
+    p = _small_cases()[name]
+    for prec, tol in ((FP64, 1e-13), (FP32, 1e-6)):
+        a = A.Graph.from_problem(p, precision=prec, driver=A.DRIVER_RESIDENT)
+        b = A.Graph.from_problem(p, precision=prec, driver=A.DRIVER_LAUNCHES)
+        assert a.info()["driver"] == A.DRIVER_RESIDENT
+        assert b.info()["driver"] == A.DRIVER_LAUNCHES
+        a.run(40)
+        b.run(40)
+        assert rel(a.z(), b.z()) <= tol and rel(a.u(), b.u()) <= tol and rel(a.x(), b.x()) <= tol
+        ra, rb_ = a.residuals(), b.residuals()
+        assert np.allclose(ra, rb_, rtol=1e-6, atol=1e-12)
+
+
+def test_resident_determinism_resume_and_profiled():
+    p = W.workload("packing_tri10")
+    a = A.Graph.from_problem(p)
+    assert a.info()["driver"] == A.DRIVER_RESIDENT      # chosen automatically
+    a.run(37)
+    b = A.Graph.from_problem(p)
+    b.run(20)
+    b.run(17)
+    assert np.array_equal(a.z(), b.z()) and np.array_equal(a.u(), b.u())
+    assert np.array_equal(a.x(), b.x())
+    c = A.Graph.from_problem(p)
+    xm, zm = c.run_profiled(37)
+    assert xm > 0 and zm == 0
+    assert np.array_equal(a.z(), c.z())
+    # the state set from the host is what the next resident run starts from
+    d = A.Graph.from_problem(p)
+    d.set_state(a.z(), a.u())
+    d.run(5)
+    a.run(5)
+    assert np.array_equal(a.z(), d.z())
