@@ -91,6 +91,8 @@ typedef struct {
   int32_t alpha_is_one;        /* 1: m-only state (alpha == 1) */
   int32_t driver;              /* ADMM_DRIVER_LAUNCHES or ADMM_DRIVER_RESIDENT */
   int32_t resident_lds_bytes;  /* LDS image of the resident driver (0 if unused) */
+  int32_t sparse_pair_state;   /* 1: pair tiles keep unmoved pairs' m implicit */
+  int32_t reserved_;
 } admm_graph_info;
 
 /* Message for the last failing call on this thread ("" if none). */
@@ -135,9 +137,20 @@ admm_status admm_graph_set_alpha(admm_graph* g, double alpha);
  *  device's per-workgroup limit): finalize returns ADMM_E_UNSUPPORTED when
  *  the graph does not fit.  ADMM_DRIVER_AUTO (default): resident when the
  *  graph fits and has at most 64 x-pass plus z-pass blocks, else launches.
- *  The arithmetic of every step is the same in both drivers. */
-enum { ADMM_OPT_PAIR_ROWS = 1, ADMM_OPT_DRIVER = 2 };
+ *  The arithmetic of every step is the same in both drivers.
+ *  ADMM_OPT_PAIR_STATE: per-edge state of dense pair tiles.  With alpha = 1
+ *  a pair whose prox leaves n unchanged (no overlap) ends the iteration with
+ *  m = z, the consensus it started from (Alg. 2: m = x + u, u = m_old - z,
+ *  x = n = 2z - m_old).  ADMM_PAIR_STATE_AUTO (default) keeps such pairs'
+ *  m implicit in FP32 with alpha = 1: one flag bit per pair, and m is only
+ *  read and written for pairs the prox moves; the next iteration takes
+ *  their m from the previous z.  Every prox is still evaluated every
+ *  iteration; the last iteration of a run stores the state of every pair.
+ *  ADMM_PAIR_STATE_DENSE reads and writes every pair's m every iteration
+ *  (always the case in FP64 or with alpha != 1). */
+enum { ADMM_OPT_PAIR_ROWS = 1, ADMM_OPT_DRIVER = 2, ADMM_OPT_PAIR_STATE = 3 };
 enum { ADMM_DRIVER_AUTO = 0, ADMM_DRIVER_LAUNCHES = 1, ADMM_DRIVER_RESIDENT = 2 };
+enum { ADMM_PAIR_STATE_AUTO = 0, ADMM_PAIR_STATE_DENSE = 1 };
 admm_status admm_graph_set_option(admm_graph* g, int32_t option, int64_t value);
 
 /* Validate, bucket factors by kind, build the device layout (edge-major

@@ -23,8 +23,9 @@ STATUS_NAMES = {0: "OK", 1: "E_ARG", 2: "E_STATE", 3: "E_NUMERIC", 4: "E_HIP",
 KIND = dict(nonoverlap=1, wall=2, radius=3, quad=4, box=5, hinge=6, l2=7,
             lindyn=8, lindyn0=9)
 FP32, FP64 = 0, 1
-OPT_PAIR_ROWS, OPT_DRIVER = 1, 2
+OPT_PAIR_ROWS, OPT_DRIVER, OPT_PAIR_STATE = 1, 2, 3
 DRIVER_AUTO, DRIVER_LAUNCHES, DRIVER_RESIDENT = 0, 1, 2
+PAIR_STATE_AUTO, PAIR_STATE_DENSE = 0, 1
 
 
 class AdmmError(RuntimeError):
@@ -39,7 +40,8 @@ class GraphInfo(ctypes.Structure):
         "n_pair_tiles", "n_contributions", "state_bytes",
         "algo_bytes_per_iter", "layout_bytes_per_iter")] + [
         ("precision", ctypes.c_int32), ("alpha_is_one", ctypes.c_int32),
-        ("driver", ctypes.c_int32), ("resident_lds_bytes", ctypes.c_int32)]
+        ("driver", ctypes.c_int32), ("resident_lds_bytes", ctypes.c_int32),
+        ("sparse_pair_state", ctypes.c_int32), ("reserved_", ctypes.c_int32)]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}
@@ -212,7 +214,8 @@ class Graph:
     @classmethod
     def from_problem(cls, problem, precision: int = FP32, device: Optional[int] = 0,
                      rho: Optional[float] = None, alpha: Optional[float] = None,
-                     pair_rows: int = 0, driver: int = DRIVER_AUTO):
+                     pair_rows: int = 0, driver: int = DRIVER_AUTO,
+                     pair_state: int = PAIR_STATE_AUTO):
         """Build from an object with var_dims, groups (kind, var_ids, params,
         shared), rho, alpha and z0.  device=None skips finalize."""
         g = cls(problem.var_dims, precision)
@@ -224,6 +227,8 @@ class Graph:
             g.set_option(OPT_PAIR_ROWS, pair_rows)
         if driver != DRIVER_AUTO:
             g.set_option(OPT_DRIVER, driver)
+        if pair_state != PAIR_STATE_AUTO:
+            g.set_option(OPT_PAIR_STATE, pair_state)
         if device is not None:
             g.finalize(device)
             g.set_state(problem.z0)

@@ -49,6 +49,7 @@ struct Plan {
   std::vector<int32_t> idx;
   std::vector<double> par;
   int64_t n_zc = 0, n_m = 0;    // contribution buffer and m-region element counts
+  int64_t zc_span = 0;          // n_zc rounded up to 64 (start of the m regions)
   std::vector<int32_t> var_b, var_w, var_l;   // z lists: long, medium, short
   std::vector<int64_t> rng_b, rng_w, rng_l;
   std::vector<double> deg_b, deg_w, deg_l;
@@ -58,6 +59,7 @@ struct Plan {
   int64_t algo_bytes = 0, layout_bytes = 0;  // per iteration, in T units x sizeof later
   int64_t algo_elems = 0, layout_idx_bytes = 0, layout_elems = 0;
   int64_t n_pair_tiles = 0;
+  int64_t n_flags = 0;          // sparse pair-state flag words (NT per tile)
   bool no_tiles = false;        // input: build no dense pair tiles
   bool resident = false;        // output of finalize: resident driver chosen
 };
@@ -89,6 +91,7 @@ struct admm_graph {
   double rho = 1.0, alpha = 1.0;
   int32_t pair_rows = 0;  // rows per dense pair tile (0: chosen at finalize)
   int32_t driver = ADMM_DRIVER_AUTO;
+  int32_t pair_state = ADMM_PAIR_STATE_AUTO;
   int64_t n_factors = 0, n_edges = 0, n_slots = 0;
   int state = 0;  // 0 building, 1 validated (no device), 2 ready
   int device = -1;
@@ -266,6 +269,7 @@ admm_status build_plan(admm_graph& g, Plan& P, bool no_tiles) {
     b.arity = gr.arity;
     b.idx_off = (int64_t)P.idx.size();
     b.par_off = (int64_t)P.par.size();
+    P.n_m = round_up(P.n_m, 64);  // every bucket's state starts 256-byte aligned
     b.m_off = P.n_m;
     // slots per factor (constant within a group for every kind but QUAD/BOX/L2)
     auto fslots = [&](int64_t f) {
@@ -304,6 +308,17 @@ admm_status build_plan(admm_graph& g, Plan& P, bool no_tiles) {
       b.n = (int64_t)tI.size();
       b.nfp = b.n;
       P.n_pair_tiles += b.n;
+      {
+        bool aff = b.E > 0;
+        for (int e = 0; e < b.E && aff; ++e)
+          aff = ezc[e] == ezc[0] + 3 * e && ezr[e] == ezc[e] + 2;
+        b.ent_aff = aff ? 1 : 0;
+        b.ent_base = aff ? ezc[0] : 0;
+      }
+      b.sparse = (g.precision == ADMM_FP32 && g.alpha == 1.0 &&
+                  g.pair_state != ADMM_PAIR_STATE_DENSE) ? 1 : 0;
+      b.flag0 = P.n_flags;
+      if (b.sparse) P.n_flags += b.n * NT;
       for (int64_t t = 0; t < b.n; ++t) { P.idx.push_back(tI[t]); P.idx.push_back(tJ[t]); }
       for (int e = 0; e < b.E; ++e) { P.idx.push_back(ezc[e]); P.idx.push_back(ezr[e]); }
       const int64_t TS = 6LL * RB * CB;
@@ -566,13 +581,15 @@ admm_status build_plan(admm_graph& g, Plan& P, bool no_tiles) {
     std::vector<int64_t> fill(cnt.begin(), cnt.end() - 1);
     for (auto& e : em) P.idx[e.key] = (int32_t)(fill[e.z]++);
   }
-  // pool = [contributions | m regions | x regions]
+  // pool = [contributions | m regions | x regions], each region aligned
+  P.n_m = round_up(P.n_m, 64);
+  P.zc_span = round_up(P.n_zc, 64);
   for (BucketDesc& b : P.bt) {
-    b.m_off += P.n_zc;
+    b.m_off += P.zc_span;
     b.x_off = b.m_off + P.n_m;
   }
-  for (auto& v : P.upos) v += P.n_zc;
-  if (P.n_zc + 2 * P.n_m > 0x7fffffffLL)
+  for (auto& v : P.upos) v += P.zc_span;
+  if (P.zc_span + 2 * P.n_m > 0x7fffffffLL)
     return admmi::set_err(ADMM_E_UNSUPPORTED, "more than 2^31 pool elements");
   for (int64_t zi = 0; zi < g.nz; ++zi) {
     const int64_t len = cnt[zi + 1] - cnt[zi];
@@ -608,7 +625,7 @@ int64_t zpass_blocks(const Plan& P) {
 // in the order resident_layout assigns them.
 int64_t resident_image_bytes(const Plan& P, int64_t nz, int64_t es) {
   auto r16 = [](int64_t b) { return (b + 15) / 16 * 16; };
-  int64_t b = r16((P.n_zc + 2 * P.n_m) * es) + 2 * r16(nz * es) + r16((int64_t)P.par.size() * es) +
+  int64_t b = r16((P.zc_span + 2 * P.n_m) * es) + 2 * r16(nz * es) + r16((int64_t)P.par.size() * es) +
               r16((int64_t)P.idx.size() * 4);
   b += r16((int64_t)P.var_b.size() * 4) + r16((int64_t)P.rng_b.size() * 8) + r16((int64_t)P.deg_b.size() * es);
   b += r16((int64_t)P.var_w.size() * 4) + r16((int64_t)P.rng_w.size() * 8) + r16((int64_t)P.deg_w.size() * es);
@@ -635,6 +652,8 @@ struct Engine : EngineBase {
   int64_t* rng_b = nullptr;
   T* deg_b = nullptr;
   bool resident = false;
+  uint16_t* flags = nullptr;
+  int64_t n_flags = 0;
   ResArgs<T> ra{};
   size_t res_lds = 0;
   T* pool = nullptr;
@@ -758,12 +777,15 @@ struct Engine : EngineBase {
     {
       int need = 0;
       for (const BucketDesc& b : P.bt) {
-        if (b.mode == BM_PAIR) need |= FT_PAIR;
+        if (b.mode == BM_PAIR) need |= b.sparse ? FT_PAIRSP : FT_PAIR;
         else if (b.mode == BM_UNIF_HINGE && b.dmax <= 32) need |= FT_UHINGE;
         else if (b.mode == BM_GEN_SLOT || b.kind == KD_NONOVERLAP || b.kind == KD_WALL) need |= FT_GEN;
         else need |= FT_WIDE;
       }
-      fs = ((need & ~FS_PAIR) == 0) ? FS_PAIR : ((need & ~FS_HINGE) == 0) ? FS_HINGE : FS_ALL;
+      fs = ((need & ~FS_PAIR) == 0)     ? FS_PAIR
+           : ((need & ~FS_PAIRSP) == 0) ? FS_PAIRSP
+           : ((need & ~FS_HINGE) == 0)  ? FS_HINGE
+                                        : FS_ALL;
     }
     n_b = (int64_t)P.var_b.size();
     n_w = (int64_t)P.var_w.size();
@@ -775,7 +797,7 @@ struct Engine : EngineBase {
     nz = (int64_t)z0.size();
     xdelta = P.n_m;
     admm_status s;
-    pool_n = P.n_zc + 2 * P.n_m;
+    pool_n = P.zc_span + 2 * P.n_m;
     par_n = (int64_t)P.par.size();
     idx_n = (int64_t)P.idx.size();
     if ((s = alloc(&pool, pool_n))) return s;
@@ -800,6 +822,8 @@ struct Engine : EngineBase {
     if ((s = alloc(&bmz, zblocks))) return s;
     io_n = std::max(n_slots, nz);
     if ((s = alloc(&io, io_n))) return s;
+    n_flags = P.n_flags;
+    if ((s = alloc(&flags, n_flags))) return s;
     if (resident) resident_layout();
     return set_state(z0.data(), nullptr, nullptr);
   }
@@ -817,6 +841,9 @@ struct Engine : EngineBase {
     if (gs)
       set_state_kernel<T><<<gs, 256, 0, st>>>(n_slots, upos, uz, uh ? io : nullptr, z[zc], pool,
                                               xdelta, 1);
+    // every pair's m is explicit in the dense arrays after a state import
+    if (n_flags)
+      fill_u16_kernel<<<(unsigned)((n_flags + 255) / 256), 256, 0, st>>>(n_flags, 0xFFFF, flags);
     ADMM_HIP(hipGetLastError());
     ADMM_HIP(hipStreamSynchronize(st));
     have_resid = false;
@@ -829,6 +856,8 @@ struct Engine : EngineBase {
     a.idx = idx;
     a.par = par;
     a.z = z[zc];
+    a.zprev = z[zc ^ 1];
+    a.flags = flags;
     a.blockmax = bmx;
     a.bt = bt;
     a.nb = nb;
@@ -854,6 +883,7 @@ struct Engine : EngineBase {
   template <bool A1>
   void launch_x(int mode, hipStream_t st, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
     if (fs == FS_PAIR) launch_x_fs<A1, FS_PAIR>(mode, st, e0, e1);
+    else if (fs == FS_PAIRSP) launch_x_fs<A1, FS_PAIRSP>(mode, st, e0, e1);
     else if (fs == FS_HINGE) launch_x_fs<A1, FS_HINGE>(mode, st, e0, e1);
     else launch_x_fs<A1, FS_ALL>(mode, st, e0, e1);
   }
@@ -1149,6 +1179,11 @@ admm_status admm_graph_set_option(admm_graph* g, int32_t option, int64_t value) 
         return admmi::set_err(ADMM_E_ARG, "pair tile rows must be 0, 16, 32 or 64");
       g->pair_rows = (int32_t)value;
       return ADMM_OK;
+    case ADMM_OPT_PAIR_STATE:
+      if (value != ADMM_PAIR_STATE_AUTO && value != ADMM_PAIR_STATE_DENSE)
+        return admmi::set_err(ADMM_E_ARG, "pair state must be 0 (auto) or 1 (dense)");
+      g->pair_state = (int32_t)value;
+      return ADMM_OK;
     case ADMM_OPT_DRIVER:
       if (value != ADMM_DRIVER_AUTO && value != ADMM_DRIVER_LAUNCHES && value != ADMM_DRIVER_RESIDENT)
         return admmi::set_err(ADMM_E_ARG, "driver must be 0 (auto), 1 (launches) or 2 (resident)");
@@ -1196,12 +1231,13 @@ admm_status admm_graph_finalize(admm_graph* g, int32_t device) {
   I.n_contributions = P.n_zc;
   I.precision = g->precision;
   I.alpha_is_one = g->alpha == 1.0;
-  I.state_bytes = (P.n_zc + 2 * P.n_m) * es;
+  I.state_bytes = (P.zc_span + 2 * P.n_m) * es;
   // algorithmic: state read + write per slot (m; plus x when alpha != 1) and
   // per-factor prox data; layout: indices, partial sums and their reads.
   I.algo_bytes_per_iter = P.algo_elems * es * (g->alpha == 1.0 ? 1 : 2);
   I.layout_bytes_per_iter = P.layout_elems * es + P.layout_idx_bytes;
   I.driver = P.resident ? ADMM_DRIVER_RESIDENT : ADMM_DRIVER_LAUNCHES;
+  I.sparse_pair_state = P.n_flags > 0 ? 1 : 0;
   I.resident_lds_bytes = P.resident ? (int32_t)resident_image_bytes(P, g->nz, es) : 0;
   if (admm_status s = admmi::probe_device(device)) {
     g->state = 1;

@@ -52,7 +52,11 @@ struct BucketDesc {
   int32_t arity, nslot; // edges / scalar slots per factor
   int32_t d, nn, mm, dmax;  // hinge d (and its register bound); lindyn n, m
   int32_t E, NB;        // pair layout: entities, column blocks
-  int32_t rb, pad_;     // pair layout: entities per row block (16, 32 or 64)
+  int32_t rb;           // pair layout: entities per row block (16, 32 or 64)
+  int32_t sparse;       // pair layout: state of unmoved pairs kept implicit (FP32, alpha = 1)
+  int64_t flag0;        // pair layout: first flag word of this bucket (per tile NT words)
+  int32_t ent_aff;      // pair layout: entity e's z offsets are ent_base + 3e (centre), + 2 (radius)
+  int32_t ent_base;
   int64_t m_off, x_off;  // element offsets of the state regions in the pool
   int64_t dst_off;      // index-buffer offset of the contribution destinations
   int64_t idx_off;      // offset in the int32 index buffer
@@ -65,6 +69,8 @@ struct XArgs {
   const int32_t* idx;
   const T* par;
   const T* z;
+  const T* zprev;       // z of the previous iteration (sparse pair state)
+  uint16_t* flags;      // sparse pair state: bit set = m stored explicitly
   T* blockmax;
   const BucketDesc* bt;
   int32_t nb;
@@ -135,11 +141,12 @@ __device__ __forceinline__ void state_un(T m, T xo, T zv, T alpha, T& u, T& n) {
 // apart along n_hat and shrink both radii by D/4, D = max(0, r1+r2-|c2-c1|);
 // n_hat = (1,0) when the centres coincide.
 template <typename T>
-__device__ __forceinline__ void prox_nonoverlap(T* v) {
+__device__ __forceinline__ bool prox_nonoverlap(T* v) {
   const T dx = v[3] - v[0], dy = v[4] - v[1];
   const T L = sqrt(dx * dx + dy * dy);
   const T D = v[2] + v[5] - L;
-  if (D > T(0)) {
+  const bool moved = D > T(0);
+  if (moved) {
     T hx = T(1), hy = T(0);
     if (L > T(0)) {
       const T il = T(1) / L;
@@ -154,6 +161,7 @@ __device__ __forceinline__ void prox_nonoverlap(T* v) {
     v[4] += st * hy;
     v[5] -= st;
   }
+  return moved;
 }
 
 // Wall Q^T(c - V) >= r; p = (Qx, Qy, Q.V, 1/(|Q|^2+1)).
@@ -287,6 +295,453 @@ __device__ __forceinline__ void xpass_pair(const XArgs<T>& a, const BucketDesc& 
       const int d = dst[3 * RB + t];
       if (d >= 0) a.pool[d] = s;
     }
+  }
+}
+
+// FP32 with alpha = 1: the same tile computation with 16-byte accesses.
+// Thread (w, rg = lane / 16, cq = lane % 16) owns columns 4cq .. 4cq+3 and
+// rows li = w*RB/4 + 4k + rg, k < RB/16, so that one load instruction of a
+// wavefront covers four whole rows (1 KB).  Every load of a thread is issued
+// before its first prox.  Row sums: over the thread's four columns, then a
+// 16-lane DPP tree (one DPP row holds exactly the lanes of one tile row).
+// Column sums: over the thread's rows, across the four DPP rows (xor 16,
+// 32), then across the four wavefronts in LDS in wavefront order.  State of
+// pairs that are not factors (lower triangle of diagonal tiles, padding) is
+// updated too but never summed or returned, so that stores cover whole rows.
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+template <int RB>
+struct PairMap {
+  static constexpr int CB = PB;
+  static constexpr int PRT = RB / 16;   // rows per thread
+  static constexpr int TSZ = RB * CB;   // pairs per tile
+  static __device__ __forceinline__ int row(int w, int k, int rg) { return w * (RB / 4) + 4 * k + rg; }
+};
+
+// z offsets of pair-tile entity e (centre x, radius).
+__device__ __forceinline__ void pair_entity(const BucketDesc& b, const int32_t* ent, int e,
+                                            int& zc, int& zr) {
+  if (b.ent_aff) {
+    zc = b.ent_base + 3 * e;
+    zr = zc + 2;
+  } else {
+    zc = ent[2 * e];
+    zr = ent[2 * e + 1];
+  }
+}
+
+// Column sums of a thread's four columns (three scalars each) across the
+// four DPP rows of its wavefront and then the four wavefronts, in a fixed
+// order; thread t < 192 returns the total for column t / 3, scalar t % 3.
+__device__ __forceinline__ float pair_colsum(float (&cs)[4][3], float (*cacc)[PB * 3], int w,
+                                            int rg, int cq, int t) {
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+      float v = cs[c][s];
+      v += __shfl_xor(v, 16, 64);
+      v += __shfl_xor(v, 32, 64);
+      cs[c][s] = v;
+    }
+  if (rg == 0) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+      for (int s = 0; s < 3; ++s) cacc[w][(4 * cq + c) * 3 + s] = cs[c][s];
+  }
+  __syncthreads();
+  float sum = 0.f;
+  if (t < PB * 3) {
+    sum = cacc[0][t];
+#pragma unroll
+    for (int q = 1; q < NT / 64; ++q) sum += cacc[q][t];
+  }
+  return sum;
+}
+
+template <int MODE, int RB>
+__device__ __forceinline__ void xpass_pair_v4(const XArgs<float>& a, const BucketDesc& b,
+                                              int tile) {
+  using PM = PairMap<RB>;
+  constexpr int CB = PM::CB, PRT = PM::PRT, TSZ = PM::TSZ;
+  __shared__ float zrow4[RB * 3];
+  __shared__ float zcol4[CB * 3];
+  __shared__ float cacc4[NT / 64][CB * 3];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int rg = lane >> 4, cq = lane & 15;
+  const int32_t* tiles = a.idx + b.idx_off;
+  const int32_t* ent = tiles + 2 * b.n;
+  const int I = tiles[2 * tile], J = tiles[2 * tile + 1];
+  constexpr int64_t TS = 6 * (int64_t)TSZ;
+  const float* src = a.pool + (MODE == PM_RESID ? b.x_off : b.m_off) + (int64_t)tile * TS;
+  f4v mv[PRT][6];
+#pragma unroll
+  for (int k = 0; k < PRT; ++k) {
+    const int li = PM::row(w, k, rg);
+#pragma unroll
+    for (int s = 0; s < 6; ++s)
+      mv[k][s] = *(const f4v*)(src + s * TSZ + li * CB + 4 * cq);
+  }
+  if (t < RB + CB) {
+    const bool isrow = t < RB;
+    const int l = isrow ? t : t - RB;
+    const int e = isrow ? I * RB + l : J * CB + l;
+    float cx = 0.f, cy = 0.f, r = 0.f;
+    if (e < b.E) {
+      int zc, zr;
+      pair_entity(b, ent, e, zc, zr);
+      cx = a.z[zc];
+      cy = a.z[zc + 1];
+      r = a.z[zr];
+    }
+    float* dst = isrow ? zrow4 : zcol4;
+    dst[l * 3 + 0] = cx;
+    dst[l * 3 + 1] = cy;
+    dst[l * 3 + 2] = r;
+  }
+  __syncthreads();
+  float zcl[4][3];
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+#pragma unroll
+    for (int s = 0; s < 3; ++s) zcl[c][s] = zcol4[(4 * cq + c) * 3 + s];
+  const int ej0 = J * CB + 4 * cq;
+  if constexpr (MODE == PM_RESID) {
+    float rmax = 0.f;
+#pragma unroll
+    for (int k = 0; k < PRT; ++k) {
+      const int li = PM::row(w, k, rg);
+      const int ei = I * RB + li;
+      float zr[3];
+#pragma unroll
+      for (int s = 0; s < 3; ++s) zr[s] = zrow4[li * 3 + s];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int ej = ej0 + c;
+        if (ei < ej && ej < b.E) {
+#pragma unroll
+          for (int s = 0; s < 6; ++s)
+            rmax = tmax(rmax, tabs(mv[k][s][c] - (s < 3 ? zr[s] : zcl[c][s - 3])));
+        }
+      }
+    }
+    block_max_store(rmax, a.blockmax);
+  } else {
+    float* mt = a.pool + b.m_off + (int64_t)tile * TS;
+    float* xt = a.pool + b.x_off + (int64_t)tile * TS;
+    const int32_t* dst = a.idx + b.dst_off + (int64_t)tile * (3 * (RB + CB));
+    float cs[4][3];
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+      for (int s = 0; s < 3; ++s) cs[c][s] = 0.f;
+#pragma unroll
+    for (int k = 0; k < PRT; ++k) {
+      const int li = PM::row(w, k, rg);
+      const int ei = I * RB + li;
+      float zr[3];
+#pragma unroll
+      for (int s = 0; s < 3; ++s) zr[s] = zrow4[li * 3 + s];
+      float rs[3] = {0.f, 0.f, 0.f};
+      f4v xv[6];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int ej = ej0 + c;
+        const bool valid = (ei < ej) && (ej < b.E);
+        float u[6], v[6];
+#pragma unroll
+        for (int s = 0; s < 6; ++s) {
+          const float zv = s < 3 ? zr[s] : zcl[c][s - 3];
+          u[s] = mv[k][s][c] - zv;
+          v[s] = zv - u[s];
+        }
+        prox_nonoverlap(v);
+#pragma unroll
+        for (int s = 0; s < 6; ++s) {
+          const float mn = v[s] + u[s];
+          mv[k][s][c] = mn;
+          xv[s][c] = v[s];
+          if (s < 3) rs[s] += valid ? mn : 0.f;
+          else cs[c][s - 3] += valid ? mn : 0.f;
+        }
+      }
+#pragma unroll
+      for (int s = 0; s < 6; ++s) {
+        *(f4v*)(mt + s * TSZ + li * CB + 4 * cq) = mv[k][s];
+        if constexpr (MODE == PM_SAVE) *(f4v*)(xt + s * TSZ + li * CB + 4 * cq) = xv[s];
+      }
+#pragma unroll
+      for (int s = 0; s < 3; ++s) rs[s] = admmi::row16_sum(rs[s]);
+      if (cq < 3) {
+        const int d = dst[li * 3 + cq];
+        if (d >= 0) a.pool[d] = cq == 0 ? rs[0] : (cq == 1 ? rs[1] : rs[2]);
+      }
+    }
+    const float sum = pair_colsum(cs, cacc4, w, rg, cq, t);
+    if (t < CB * 3) {
+      const int d = dst[3 * RB + t];
+      if (d >= 0) a.pool[d] = sum;
+    }
+  }
+}
+
+// Sparse pair state (b.sparse; FP32, alpha = 1, x-pass modes NORMAL and
+// SAVE).  A pair whose prox leaves n where it is (no overlap) ends the
+// iteration with m = n + u = z exactly, the z the iteration started from.
+// Such a pair stores nothing: its bit in the thread's 16-bit flag word is
+// cleared, and the next iteration takes its m from the previous z.  Only
+// pairs the prox moves store m (whole float4 rows of the thread, read back
+// only where the flag is set).  Every pair's prox is evaluated every
+// iteration: for a pair with implicit m, n and u depend on the two entities
+// only and are formed once per entity (u = z_prev - z, n = z - u, the same
+// formulas as for stored m); the overlap test D = r_i + r_j - |c_j - c_i| > 0
+// is first taken without the square root, with a relative margin of 2^-18
+// on |c_j - c_i|^2 (far above the rounding of the squares and of the root),
+// and only pairs inside the margin or with stored m go through the full
+// operator, so every decision equals the operator's own.  An unmoved pair
+// contributes z to both partial sums: a row's partial is the sum of its
+// moved pairs' m plus (valid pairs - moved pairs) * z, the valid count
+// being known from the tile position; the DPP and cross-wavefront sums of
+// the moved pairs are skipped when no pair of the wavefront (workgroup)
+// moved.  All independent loads (flags, destinations, z of both
+// iterations) are issued together at the start.  The last iteration of a
+// run stores m and x of every pair and sets every flag, so that the dense
+// arrays are complete between runs.
+template <int MODE, int RB>
+__device__ __forceinline__ void xpass_pair_sparse(const XArgs<float>& a, const BucketDesc& b,
+                                                  int tile) {
+  using PM = PairMap<RB>;
+  constexpr int CB = PM::CB, PRT = PM::PRT, TSZ = PM::TSZ;
+  constexpr bool SAVE = MODE == PM_SAVE;
+  __shared__ float erow[3][RB * 3];   // z, n, u of the row entities
+  __shared__ float ecol[3][CB * 3];   // z, n, u of the column entities
+  __shared__ float cacc5[NT / 64][CB * 3];
+  __shared__ float cnt5[NT / 64][CB];
+  __shared__ int any5;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int rg = lane >> 4, cq = lane & 15;
+  const int32_t* tiles = a.idx + b.idx_off;
+  const int32_t* ent = tiles + 2 * b.n;
+  const int I = tiles[2 * tile], J = tiles[2 * tile + 1];
+  constexpr int64_t TS = 6 * (int64_t)TSZ;
+  uint16_t* flagp = a.flags + b.flag0 + (int64_t)tile * NT + t;
+  const uint32_t fl = *flagp;       // set: m of the pair is stored
+  const int32_t* dst = a.idx + b.dst_off + (int64_t)tile * (3 * (RB + CB));
+  int drow[PRT];
+#pragma unroll
+  for (int k = 0; k < PRT; ++k) drow[k] = cq < 3 ? dst[PM::row(w, k, rg) * 3 + cq] : -1;
+  const int dcol = t < CB * 3 ? dst[3 * RB + t] : -1;
+  if (t < RB + CB) {
+    const bool isrow = t < RB;
+    const int l = isrow ? t : t - RB;
+    const int e = isrow ? I * RB + l : J * CB + l;
+    float zv[3] = {0.f, 0.f, 0.f}, zp[3] = {0.f, 0.f, 0.f};
+    if (e < b.E) {
+      int zc, zr;
+      pair_entity(b, ent, e, zc, zr);
+      zv[0] = a.z[zc];
+      zv[1] = a.z[zc + 1];
+      zv[2] = a.z[zr];
+      zp[0] = a.zprev[zc];
+      zp[1] = a.zprev[zc + 1];
+      zp[2] = a.zprev[zr];
+    }
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+      const float u = zp[s] - zv[s];
+      const float n = zv[s] - u;
+      if (isrow) {
+        erow[0][l * 3 + s] = zv[s];
+        erow[1][l * 3 + s] = n;
+        erow[2][l * 3 + s] = u;
+      } else {
+        ecol[0][l * 3 + s] = zv[s];
+        ecol[1][l * 3 + s] = n;
+        ecol[2][l * 3 + s] = u;
+      }
+    }
+  }
+  if (t == 0) any5 = 0;
+  __syncthreads();
+  float cz[4][3], cn[4][3];
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+      cz[c][s] = ecol[0][(4 * cq + c) * 3 + s];
+      cn[c][s] = ecol[1][(4 * cq + c) * 3 + s];
+    }
+  const int ej0 = J * CB + 4 * cq;
+  // pairs that need the full operator: factors (e_i < e_j < E) with stored
+  // m or whose overlap the test does not exclude; the last iteration of a
+  // run takes every factor through it.  Other tile slots (the lower
+  // triangle and the diagonal of diagonal tiles, padding) are never
+  // evaluated: their state is not part of the method.
+  uint32_t valid = 0;
+#pragma unroll
+  for (int k = 0; k < PRT; ++k) {
+    const int ei = I * RB + PM::row(w, k, rg);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int ej = ej0 + c;
+      valid |= ((ei < ej && ej < b.E) ? 1u : 0u) << (4 * k + c);
+    }
+  }
+  uint32_t work = SAVE ? valid : (fl & valid);
+  if constexpr (!SAVE) {
+#pragma unroll
+    for (int k = 0; k < PRT; ++k) {
+      const int li = PM::row(w, k, rg);
+      const float r0 = erow[1][li * 3 + 0], r1 = erow[1][li * 3 + 1], r2 = erow[1][li * 3 + 2];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const float dx = cn[c][0] - r0, dy = cn[c][1] - r1;
+        const float S = r2 + cn[c][2];
+        const float L2 = dx * dx + dy * dy;
+        const bool maybe = S > 0.f && S * S >= L2 * (1.f - 0x1p-18f);
+        work |= (maybe ? 1u : 0u) << (4 * k + c);
+      }
+    }
+    work &= valid;
+  }
+  float* mt = a.pool + b.m_off + (int64_t)tile * TS;
+  float* xt = a.pool + b.x_off + (int64_t)tile * TS;
+  float rs[PRT][3], rmc[PRT], cs[4][3], cmc[4];
+#pragma unroll
+  for (int k = 0; k < PRT; ++k) {
+    rmc[k] = 0.f;
+#pragma unroll
+    for (int s = 0; s < 3; ++s) rs[k][s] = 0.f;
+  }
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    cmc[c] = 0.f;
+#pragma unroll
+    for (int s = 0; s < 3; ++s) cs[c][s] = 0.f;
+  }
+  uint32_t movedall = 0;
+  if (work) {
+#pragma unroll
+    for (int k = 0; k < PRT; ++k) {
+      const uint32_t rowwork = (work >> (4 * k)) & 0xFu;
+      if (!rowwork) continue;
+      const int li = PM::row(w, k, rg);
+      const uint32_t rowbits = (fl >> (4 * k)) & 0xFu;
+      f4v mv[6];
+      if (rowbits) {
+#pragma unroll
+        for (int s = 0; s < 6; ++s)
+          mv[s] = *(const f4v*)(mt + s * TSZ + li * CB + 4 * cq);
+      }
+      float rz[3], rn[3], ru[3];
+#pragma unroll
+      for (int s = 0; s < 3; ++s) {
+        rz[s] = erow[0][li * 3 + s];
+        rn[s] = erow[1][li * 3 + s];
+        ru[s] = erow[2][li * 3 + s];
+      }
+      f4v mo[6], xo[6];
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+#pragma unroll
+        for (int s = 0; s < 6; ++s) {
+          mo[s][c] = s < 3 ? rz[s] : cz[c][s - 3];
+          xo[s][c] = s < 3 ? rn[s] : cn[c][s - 3];
+        }
+      uint32_t moved_bits = 0;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        if (!((rowwork >> c) & 1u)) continue;
+        const bool expl = (rowbits >> c) & 1u;
+        float u[6], v[6];
+#pragma unroll
+        for (int s = 0; s < 6; ++s) {
+          if (expl) {
+            const float zv = s < 3 ? rz[s] : cz[c][s - 3];
+            u[s] = mv[s][c] - zv;
+            v[s] = zv - u[s];
+          } else {
+            u[s] = s < 3 ? ru[s] : ecol[2][(4 * cq + c) * 3 + s - 3];
+            v[s] = s < 3 ? rn[s] : cn[c][s - 3];
+          }
+        }
+        const bool moved = prox_nonoverlap(v);
+#pragma unroll
+        for (int s = 0; s < 6; ++s) xo[s][c] = v[s];
+        if (moved) {
+          moved_bits |= 1u << c;
+#pragma unroll
+          for (int s = 0; s < 6; ++s) mo[s][c] = v[s] + u[s];
+#pragma unroll
+          for (int s = 0; s < 3; ++s) {
+            rs[k][s] += mo[s][c];
+            cs[c][s] += mo[s + 3][c];
+          }
+          rmc[k] += 1.f;
+          cmc[c] += 1.f;
+        }
+      }
+      if (SAVE || moved_bits) {
+#pragma unroll
+        for (int s = 0; s < 6; ++s) {
+          *(f4v*)(mt + s * TSZ + li * CB + 4 * cq) = mo[s];
+          if constexpr (SAVE) *(f4v*)(xt + s * TSZ + li * CB + 4 * cq) = xo[s];
+        }
+      }
+      movedall |= moved_bits << (4 * k);
+    }
+  }
+  *flagp = (uint16_t)(SAVE ? 0xFFFFu : movedall);
+  // row partials: moved pairs' m plus (valid - moved) * z
+  const bool wave_moved = __ballot(movedall != 0) != 0;
+#pragma unroll
+  for (int k = 0; k < PRT; ++k) {
+    const int li = PM::row(w, k, rg);
+    const int ei = I * RB + li;
+    const int lo = ei + 1 > J * CB ? ei + 1 : J * CB;
+    const int hi = b.E < J * CB + CB ? b.E : J * CB + CB;
+    float cnt = (float)(hi > lo ? hi - lo : 0);
+    float ms[3] = {0.f, 0.f, 0.f};
+    if (wave_moved) {
+#pragma unroll
+      for (int s = 0; s < 3; ++s) ms[s] = admmi::row16_sum(rs[k][s]);
+      cnt -= admmi::row16_sum(rmc[k]);
+    }
+    if (drow[k] >= 0) {
+      const float m = cq == 0 ? ms[0] : (cq == 1 ? ms[1] : ms[2]);
+      a.pool[drow[k]] = fmaf(cnt, erow[0][li * 3 + (cq < 3 ? cq : 0)], m);
+    }
+  }
+  // column partials
+  if (wave_moved && lane == 0) any5 = 1;
+  __syncthreads();
+  float ms = 0.f, mcnt = 0.f;
+  if (any5) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      float v = cmc[c];
+      v += __shfl_xor(v, 16, 64);
+      v += __shfl_xor(v, 32, 64);
+      cmc[c] = v;
+    }
+    if (rg == 0) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) cnt5[w][4 * cq + c] = cmc[c];
+    }
+    ms = pair_colsum(cs, cacc5, w, rg, cq, t);
+    if (t < CB * 3) {
+      const int col = t / 3;
+      mcnt = cnt5[0][col];
+#pragma unroll
+      for (int q = 1; q < NT / 64; ++q) mcnt += cnt5[q][col];
+    }
+  }
+  if (dcol >= 0) {
+    const int ej = J * CB + t / 3;
+    const int rows = ej < b.E ? (ej - I * RB < RB ? ej - I * RB : RB) : 0;
+    const float cnt = (float)(rows > 0 ? rows : 0) - mcnt;
+    a.pool[dcol] = fmaf(cnt, ecol[0][t], ms);
   }
 }
 
@@ -617,10 +1072,12 @@ enum Features : int {
   FT_UHINGE = 2,   // shared-variable hinge, d <= 32
   FT_GEN = 4,      // non-overlap/wall on arbitrary variables, separable slots
   FT_WIDE = 8,     // hinge with d <= 64, general hinge, linear dynamics
+  FT_PAIRSP = 16,  // dense pair tiles with sparse pair state
 };
 constexpr int FS_PAIR = FT_PAIR | FT_GEN;
+constexpr int FS_PAIRSP = FT_PAIRSP | FT_GEN;
 constexpr int FS_HINGE = FT_UHINGE | FT_GEN;
-constexpr int FS_ALL = FT_PAIR | FT_UHINGE | FT_GEN | FT_WIDE;
+constexpr int FS_ALL = FT_PAIR | FT_UHINGE | FT_GEN | FT_WIDE | FT_PAIRSP;
 
 // One x-pass workgroup's work; blk indexes the x-pass blocks of all buckets.
 template <typename T, bool A1, int MODE, int FS>
@@ -630,13 +1087,35 @@ __device__ __forceinline__ void xpass_block(XArgs<T> a, int blk) {
   while (bi + 1 < a.nb && blk >= a.bt[bi].blk1) ++bi;
   const BucketDesc b = a.bt[bi];
   const int local = blk - b.blk0;
-  if ((FS & FT_PAIR) && b.mode == BM_PAIR) {
-    if (b.rb == 16)
-      xpass_pair<T, A1, MODE, 16>(a, b, local);
-    else if (b.rb == 32)
-      xpass_pair<T, A1, MODE, 32>(a, b, local);
-    else
-      xpass_pair<T, A1, MODE, 64>(a, b, local);
+  if ((FS & (FT_PAIR | FT_PAIRSP)) && b.mode == BM_PAIR) {
+    if constexpr (sizeof(T) == 4 && A1) {
+      if constexpr ((FS & FT_PAIRSP) && MODE != PM_RESID) {
+        if (b.sparse) {
+          if (b.rb == 16)
+            xpass_pair_sparse<MODE, 16>(a, b, local);
+          else if (b.rb == 32)
+            xpass_pair_sparse<MODE, 32>(a, b, local);
+          else
+            xpass_pair_sparse<MODE, 64>(a, b, local);
+          return;
+        }
+      }
+      if constexpr ((FS & FT_PAIR) || MODE == PM_RESID) {
+        if (b.rb == 16)
+          xpass_pair_v4<MODE, 16>(a, b, local);
+        else if (b.rb == 32)
+          xpass_pair_v4<MODE, 32>(a, b, local);
+        else
+          xpass_pair_v4<MODE, 64>(a, b, local);
+      }
+    } else {
+      if (b.rb == 16)
+        xpass_pair<T, A1, MODE, 16>(a, b, local);
+      else if (b.rb == 32)
+        xpass_pair<T, A1, MODE, 32>(a, b, local);
+      else
+        xpass_pair<T, A1, MODE, 64>(a, b, local);
+    }
   } else if ((FS & (FT_UHINGE | FT_WIDE)) && b.mode == BM_UNIF_HINGE) {
     if ((FS & FT_UHINGE) && b.dmax <= 32)
       xpass_hinge<T, A1, MODE, true, 32>(a, b, local);
@@ -768,7 +1247,6 @@ __global__ __launch_bounds__(NT) void resident_kernel(XArgs<T> xa, ZArgs<T> za, 
     for (int i = threadIdx.x; i < r.reg[q].words; i += NT) dst[i] = src[i];
   }
   __syncthreads();
-  T* zb[2] = {(T*)(lds_img + r.o_z0), (T*)(lds_img + r.o_z1)};
   xa.pool = (T*)(lds_img + r.o_pool);
   xa.par = (const T*)(lds_img + r.o_par);
   xa.idx = (const int32_t*)(lds_img + r.o_idx);
@@ -782,10 +1260,14 @@ __global__ __launch_bounds__(NT) void resident_kernel(XArgs<T> xa, ZArgs<T> za, 
   za.var_l = (const int32_t*)(lds_img + r.o_var_l);
   za.rng_l = (const int64_t*)(lds_img + r.o_rng_l);
   za.deg_l = (const T*)(lds_img + r.o_deg_l);
+  // z buffers are addressed as lds_img + offset each iteration (not through a
+  // pointer carried across iterations) so that every z access stays an LDS
+  // access.
   int zc = r.zc;
+  const int32_t zoff[2] = {r.o_z0, r.o_z1};
   for (int k = 0; k < r.iters; ++k) {
     const bool last = (k == r.iters - 1);
-    xa.z = zb[zc];
+    xa.z = (const T*)(lds_img + zoff[zc]);
     for (int b = 0; b < r.xblocks; ++b) {
       if (A1 && last)
         xpass_block<T, A1, PM_SAVE, FS_RES>(xa, b);
@@ -793,8 +1275,8 @@ __global__ __launch_bounds__(NT) void resident_kernel(XArgs<T> xa, ZArgs<T> za, 
         xpass_block<T, A1, PM_NORMAL, FS_RES>(xa, b);
       __syncthreads();
     }
-    za.zin = zb[zc];
-    za.zout = zb[zc ^ 1];
+    za.zin = (const T*)(lds_img + zoff[zc]);
+    za.zout = (T*)(lds_img + zoff[zc ^ 1]);
     za.check = last ? 1 : 0;
     for (int b = 0; b < r.zblocks; ++b) {
       zpass_block<T>(za, b);
@@ -802,7 +1284,7 @@ __global__ __launch_bounds__(NT) void resident_kernel(XArgs<T> xa, ZArgs<T> za, 
     }
     zc ^= 1;
   }
-  xa.z = zb[zc];
+  xa.z = (const T*)(lds_img + zoff[zc]);
   for (int b = 0; b < r.xblocks; ++b) {
     xpass_block<T, A1, PM_RESID, FS_RES>(xa, b);
     __syncthreads();
@@ -813,7 +1295,7 @@ __global__ __launch_bounds__(NT) void resident_kernel(XArgs<T> xa, ZArgs<T> za, 
     uint32_t* dst = (uint32_t*)r.reg[q].back;
     for (int i = threadIdx.x; i < r.reg[q].words; i += NT) dst[i] = src[i];
   }
-  const uint32_t* zs = (const uint32_t*)zb[zc];
+  const uint32_t* zs = (const uint32_t*)(lds_img + zoff[zc]);
   uint32_t* zd = (uint32_t*)r.z_back[zc];
   for (int i = threadIdx.x; i < r.z_words; i += NT) zd[i] = zs[i];
 }
@@ -852,6 +1334,11 @@ __global__ void get_slots_kernel(int64_t ns, const int64_t* upos, const int32_t*
     u = (pool[p] - xo) + alpha * (xo - zv);
   }
   out[i] = (double)u;
+}
+
+__global__ void fill_u16_kernel(int64_t n, uint16_t v, uint16_t* out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = v;
 }
 
 template <typename T>

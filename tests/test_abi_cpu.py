@@ -96,6 +96,15 @@ def test_driver_selection():
         assert i64["resident_lds_bytes"] > i32["resident_lds_bytes"]
 
 
+def test_sparse_pair_state_selection():
+    p = W.workload("packing_sq2000")
+    for kw, want in ((dict(), 1), (dict(pair_state=A.PAIR_STATE_DENSE), 0),
+                     (dict(precision=A.FP64), 0), (dict(alpha=1.5), 0)):
+        g = A.Graph.from_problem(p, device=None, **kw)
+        assert _finalize_cpu(g) in (A.OK, A.E_NO_DEVICE)
+        assert g.info()["sparse_pair_state"] == want, kw
+
+
 def test_svm_layout():
     p = W.svm(5000, 20, seed=3)
     g = A.Graph.from_problem(p, device=None)
@@ -144,6 +153,7 @@ def test_validation_errors():
     _expect(A.E_ARG, g.set_alpha, 0.0)
     _expect(A.E_ARG, g.set_option, A.OPT_PAIR_ROWS, 48)
     _expect(A.E_ARG, g.set_option, A.OPT_DRIVER, 3)
+    _expect(A.E_ARG, g.set_option, A.OPT_PAIR_STATE, 2)
     _expect(A.E_ARG, g.set_option, 99, 1)
 
 

@@ -105,6 +105,19 @@ def test_packing_tiles_ragged_fp64(N, shape, seed, rb):
     _one_step(p, 40, FP64, 1e-12, pair_rows=rb, driver=A.DRIVER_LAUNCHES)
 
 
+@pytest.mark.parametrize("rb", [16, 32, 64])
+@pytest.mark.parametrize("N,shape,seed", [(2, "square", 1), (65, "square", 3),
+                                          (130, "triangle", 7), (200, "square", 4)])
+def test_packing_tiles_ragged_fp32(N, shape, seed, rb):
+    """FP32 with alpha = 1 takes the 16-byte tile path: one step from a common
+    state against the oracle, including residuals and x, on ragged sizes."""
+    p = W.packing(N, shape, 0.3 / np.sqrt(N), seed=seed)
+    _one_step(p, 40, FP32, 1e-5, pair_rows=rb, driver=A.DRIVER_LAUNCHES)
+    g = A.Graph.from_problem(p, pair_rows=rb, driver=A.DRIVER_LAUNCHES)
+    assert g.info()["n_pair_tiles"] == len({(i // rb, j // 64) for i in range(N)
+                                            for j in range(i + 1, N)})
+
+
 @pytest.mark.parametrize("N,seed", [(65, 12), (200, 12)])
 def test_packing_tiles_fp32(N, seed):
     p = W.packing(N, "square", 0.3 / np.sqrt(N), seed=seed)
@@ -218,21 +231,27 @@ def test_determinism_and_resume():
     assert np.array_equal(a.z(), d.z())
 
 
-def _one_step(problem, warm_iters, prec, tol, alpha=None, pair_rows=0, driver=A.DRIVER_AUTO):
+def _one_step(problem, warm_iters, prec, tol, alpha=None, pair_rows=0, driver=A.DRIVER_AUTO,
+              steps=1, pair_state=A.PAIR_STATE_AUTO):
     """Run the GPU warm_iters iterations, hand its (z, u) to both sides and
-    compare one further iteration element by element (no trajectory
-    sensitivity involved), then check that the duals around every variable
-    sum to zero (Algorithm 2 with u0 = 0 keeps that at any size)."""
+    compare `steps` further iterations element by element (one or a few
+    steps: no trajectory sensitivity involved; from the second step on, the
+    sparse pair state takes unmoved pairs' m from the previous z), then
+    check that the duals around every variable sum to zero (Algorithm 2
+    with u0 = 0 keeps that at any size)."""
     g = A.Graph.from_problem(problem, precision=prec, alpha=alpha, pair_rows=pair_rows,
-                             driver=driver)
+                             driver=driver, pair_state=pair_state)
     g.run(warm_iters)
     z, u = g.z(), g.u()
     g.set_state(z, u)
     o = O.OracleGraph(problem, alpha=alpha)
     o.set_state(z, u)
-    g.run(1)
-    o.run(1)
+    g.run(steps)
+    o.run(steps)
     _check(g, o, tol)
+    (r, s), (ro, so) = g.residuals(), o.residuals()
+    zmax = np.max(np.abs(o.z)) + 1.0
+    assert abs(r - ro) <= tol * zmax and abs(s - so) <= tol * zmax, (r, ro, s, so)
     sz = slot_z(problem)
     us = np.bincount(sz, weights=g.u(), minlength=problem.n_scalars)
     zz = g.z()
@@ -244,6 +263,34 @@ def _one_step(problem, warm_iters, prec, tol, alpha=None, pair_rows=0, driver=A.
 @pytest.mark.parametrize("rb", [16, 32, 64])
 def test_full_size_packing_2000_one_step(rb):
     _one_step(W.workload("packing_sq2000"), 20, FP32, 1e-5, pair_rows=rb)
+
+
+@pytest.mark.parametrize("pair_state", [A.PAIR_STATE_AUTO, A.PAIR_STATE_DENSE])
+def test_full_size_packing_2000_three_steps(pair_state):
+    p = W.workload("packing_sq2000")
+    g = A.Graph.from_problem(p, pair_state=pair_state)
+    assert g.info()["sparse_pair_state"] == (1 if pair_state == A.PAIR_STATE_AUTO else 0)
+    _one_step(p, 20, FP32, 1e-5, steps=3, pair_state=pair_state)
+
+
+@pytest.mark.parametrize("N,shape,seed", [(2, "square", 1), (65, "square", 3),
+                                          (130, "triangle", 7), (200, "square", 4)])
+def test_sparse_pair_state_matches_dense(N, shape, seed):
+    """Sparse and dense pair state compute the same iteration (unmoved pairs
+    end at m = z exactly instead of (z - u) + u).  From the same start the
+    two FP32 trajectories differ by rounding per iteration, which disks in
+    contact amplify over eight iterations to ~1e-5: the cross-check bar is
+    1e-4.  The element-wise bar is the oracle's, from a common state over
+    four steps (the steps after the first use the implicit m)."""
+    p = W.packing(N, shape, 0.3 / np.sqrt(N), seed=seed)
+    gs = A.Graph.from_problem(p, driver=A.DRIVER_LAUNCHES)
+    gd = A.Graph.from_problem(p, driver=A.DRIVER_LAUNCHES, pair_state=A.PAIR_STATE_DENSE)
+    assert gs.info()["sparse_pair_state"] == 1 and gd.info()["sparse_pair_state"] == 0
+    gs.run(8)
+    gd.run(8)
+    assert rel(gs.z(), gd.z()) < 1e-4 and rel(gs.x(), gd.x()) < 1e-4
+    for st in (A.PAIR_STATE_AUTO, A.PAIR_STATE_DENSE):
+        _one_step(p, 30, FP32, 1e-5, steps=4, driver=A.DRIVER_LAUNCHES, pair_state=st)
 
 
 def test_full_size_svm_100k_one_step():
@@ -332,3 +379,27 @@ def test_resident_determinism_resume_and_profiled():
     d.run(5)
     a.run(5)
     assert np.array_equal(a.z(), d.z())
+
+
+def _split_centres_radii(p):
+    """The same packing with variables reordered as all centres, then all
+    radii: pair-tile entities then need their z offsets from the table."""
+    N = p.var_dims.size // 2
+    new = np.empty(2 * N, dtype=np.int64)
+    new[0::2] = np.arange(N)
+    new[1::2] = N + np.arange(N)
+    dims = np.r_[np.full(N, 2, np.int32), np.ones(N, np.int32)]
+    z_old = p.z0.reshape(N, 3)
+    z0 = np.r_[z_old[:, :2].ravel(), z_old[:, 2]]
+    groups = [W.FactorGroup(gr.kind, new[gr.var_ids].astype(np.int32), gr.params, gr.shared)
+              for gr in p.groups]
+    return W.Problem(p.name + "_split", dims, groups, z0, rho=p.rho, alpha=p.alpha)
+
+
+@pytest.mark.parametrize("pair_state", [A.PAIR_STATE_AUTO, A.PAIR_STATE_DENSE])
+def test_pair_tiles_with_entity_table(pair_state):
+    p = _split_centres_radii(W.packing(130, "square", 0.3 / np.sqrt(130), seed=7))
+    g = A.Graph.from_problem(p, driver=A.DRIVER_LAUNCHES, pair_state=pair_state)
+    assert g.info()["n_pair_tiles"] > 0
+    _one_step(p, 30, FP32, 1e-5, steps=3, driver=A.DRIVER_LAUNCHES, pair_state=pair_state)
+    _traj(p, 12, FP64, 1e-9, driver=A.DRIVER_LAUNCHES)
