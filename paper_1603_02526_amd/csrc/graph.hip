@@ -49,9 +49,11 @@ struct Plan {
   std::vector<int32_t> idx;
   std::vector<double> par;
   int64_t n_zc = 0, n_m = 0;    // contribution buffer and m-region element counts
-  int64_t zc_span = 0;          // n_zc rounded up to 64 (start of the m regions)
+  int64_t zc_span = 0;          // contribution region incl. padding, rounded up to 64
+  int64_t w_stride = 0;         // medium z lists: fixed stride (0: explicit ranges)
+  int64_t w_base = 0, l_base = 0;  // medium / short z lists: first pool position
   std::vector<int32_t> var_b, var_w, var_l;   // z lists: long, medium, short
-  std::vector<int64_t> rng_b, rng_w, rng_l;
+  std::vector<int64_t> rng_b, rng_w;
   std::vector<double> deg_b, deg_w, deg_l;
   std::vector<int64_t> upos;    // user slot -> pool position of m
   std::vector<int32_t> uz;      // user slot -> z index
@@ -571,19 +573,62 @@ admm_status build_plan(admm_graph& g, Plan& P, bool no_tiles) {
   if (us != g.n_slots) return admmi::set_err(ADMM_E_ARG, "internal: slot count mismatch");
   if (blocks > 0x7fffffff) return admmi::set_err(ADMM_E_UNSUPPORTED, "graph too large for one launch");
   P.xblocks = blocks;
-  // Contribution positions: counting sort by z index (emission order kept
-  // within a scalar), so that each scalar's contributions are contiguous.
+  // Contribution positions.  Each scalar's contributions are contiguous, in
+  // emission order.  Long lists (more than ZB_MIN) are packed one after the
+  // other and found through explicit ranges.  Medium lists get one fixed
+  // stride, the longest of them rounded up to the lanes that sum one list,
+  // when that at most doubles their space (else explicit ranges), and short
+  // lists a stride of LANE_MAX: the z-pass then reads them without first
+  // reading a range.  Padding is never written and stays zero.
   P.n_zc = (int64_t)em.size();
-  std::vector<int64_t> cnt(g.nz + 1, 0);
-  for (auto& e : em) cnt[e.z + 1]++;
-  for (int64_t i = 0; i < g.nz; ++i) cnt[i + 1] += cnt[i];
+  std::vector<int64_t> len(g.nz, 0);
+  for (auto& e : em) len[e.z]++;
+  int64_t sum_w = 0, max_w = 0, n_wl = 0, n_ll = 0, sum_b = 0;
+  for (int64_t zi = 0; zi < g.nz; ++zi) {
+    if (len[zi] > ZB_MIN) sum_b += len[zi];
+    else if (len[zi] > LANE_MAX) { sum_w += len[zi]; max_w = std::max(max_w, len[zi]); ++n_wl; }
+    else ++n_ll;
+  }
+  const int64_t S_w = round_up(std::max<int64_t>(max_w, 1), ZSEG);
+  const bool pad_w = n_wl > 0 && S_w * n_wl <= 2 * sum_w + 4096;
+  P.w_stride = pad_w ? S_w : 0;
+  P.w_base = round_up(sum_b, 16);
+  P.l_base = round_up(P.w_base + (pad_w ? S_w * n_wl : sum_w), 16);
+  const int64_t zc_total = P.l_base + LANE_MAX * n_ll;
+  std::vector<int64_t> base(g.nz, 0);
   {
-    std::vector<int64_t> fill(cnt.begin(), cnt.end() - 1);
-    for (auto& e : em) P.idx[e.key] = (int32_t)(fill[e.z]++);
+    int64_t pb = 0, pw = P.w_base, kw = 0, kl = 0;
+    for (int64_t zi = 0; zi < g.nz; ++zi) {
+      const int64_t L = len[zi];
+      if (L > ZB_MIN) {
+        base[zi] = pb;
+        P.var_b.push_back((int32_t)zi);
+        P.rng_b.push_back(pb);
+        P.rng_b.push_back(pb + L);
+        P.deg_b.push_back((double)deg[zi]);
+        pb += L;
+      } else if (L > LANE_MAX) {
+        base[zi] = pad_w ? P.w_base + kw * S_w : pw;
+        P.var_w.push_back((int32_t)zi);
+        if (!pad_w) {
+          P.rng_w.push_back(pw);
+          P.rng_w.push_back(pw + L);
+          pw += L;
+        }
+        P.deg_w.push_back((double)deg[zi]);
+        ++kw;
+      } else {
+        base[zi] = P.l_base + kl * LANE_MAX;
+        P.var_l.push_back((int32_t)zi);
+        P.deg_l.push_back((double)deg[zi]);
+        ++kl;
+      }
+    }
+    for (auto& e : em) P.idx[e.key] = (int32_t)(base[e.z]++);
   }
   // pool = [contributions | m regions | x regions], each region aligned
   P.n_m = round_up(P.n_m, 64);
-  P.zc_span = round_up(P.n_zc, 64);
+  P.zc_span = round_up(zc_total, 64);
   for (BucketDesc& b : P.bt) {
     b.m_off += P.zc_span;
     b.x_off = b.m_off + P.n_m;
@@ -591,25 +636,6 @@ admm_status build_plan(admm_graph& g, Plan& P, bool no_tiles) {
   for (auto& v : P.upos) v += P.zc_span;
   if (P.zc_span + 2 * P.n_m > 0x7fffffffLL)
     return admmi::set_err(ADMM_E_UNSUPPORTED, "more than 2^31 pool elements");
-  for (int64_t zi = 0; zi < g.nz; ++zi) {
-    const int64_t len = cnt[zi + 1] - cnt[zi];
-    if (len > ZB_MIN) {
-      P.var_b.push_back((int32_t)zi);
-      P.rng_b.push_back(cnt[zi]);
-      P.rng_b.push_back(cnt[zi + 1]);
-      P.deg_b.push_back((double)deg[zi]);
-    } else if (len > LANE_MAX) {
-      P.var_w.push_back((int32_t)zi);
-      P.rng_w.push_back(cnt[zi]);
-      P.rng_w.push_back(cnt[zi + 1]);
-      P.deg_w.push_back((double)deg[zi]);
-    } else {
-      P.var_l.push_back((int32_t)zi);
-      P.rng_l.push_back(cnt[zi]);
-      P.rng_l.push_back(cnt[zi + 1]);
-      P.deg_l.push_back((double)std::max<int64_t>(deg[zi], 1));
-    }
-  }
   // each contribution is written once and read once; its destination index read once
   P.layout_elems += 2 * P.n_zc;
   P.layout_idx_bytes += P.n_zc * 4;
@@ -629,7 +655,7 @@ int64_t resident_image_bytes(const Plan& P, int64_t nz, int64_t es) {
               r16((int64_t)P.idx.size() * 4);
   b += r16((int64_t)P.var_b.size() * 4) + r16((int64_t)P.rng_b.size() * 8) + r16((int64_t)P.deg_b.size() * es);
   b += r16((int64_t)P.var_w.size() * 4) + r16((int64_t)P.rng_w.size() * 8) + r16((int64_t)P.deg_w.size() * es);
-  b += r16((int64_t)P.var_l.size() * 4) + r16((int64_t)P.rng_l.size() * 8) + r16((int64_t)P.deg_l.size() * es);
+  b += r16((int64_t)P.var_l.size() * 4) + r16((int64_t)P.deg_l.size() * es);
   return b;
 }
 
@@ -648,6 +674,7 @@ struct Engine : EngineBase {
   int fs = FS_ALL;  // x-pass feature set
   int64_t xblocks = 0, zblocks = 0, nb_w = 0, n_w = 0, n_l = 0, n_slots = 0, nz = 0, xdelta = 0;
   int64_t n_b = 0;
+  int64_t w_stride = 0, w_base = 0, l_base = 0;
   int32_t *var_b = nullptr;
   int64_t* rng_b = nullptr;
   T* deg_b = nullptr;
@@ -663,7 +690,7 @@ struct Engine : EngineBase {
   T* z[2] = {nullptr, nullptr};
   int zc = 0;
   int32_t *var_w = nullptr, *var_l = nullptr;
-  int64_t *rng_w = nullptr, *rng_l = nullptr;
+  int64_t* rng_w = nullptr;
   T *deg_w = nullptr, *deg_l = nullptr;
   int64_t* upos = nullptr;
   int32_t* uz = nullptr;
@@ -752,10 +779,9 @@ struct Engine : EngineBase {
     r.o_rng_b = add(rng_b, nullptr, n_b * 16);
     r.o_deg_b = add(deg_b, nullptr, n_b * es);
     r.o_var_w = add(var_w, nullptr, n_w * 4);
-    r.o_rng_w = add(rng_w, nullptr, n_w * 16);
+    r.o_rng_w = add(rng_w, nullptr, w_stride ? 0 : n_w * 16);
     r.o_deg_w = add(deg_w, nullptr, n_w * es);
     r.o_var_l = add(var_l, nullptr, n_l * 4);
-    r.o_rng_l = add(rng_l, nullptr, n_l * 16);
     r.o_deg_l = add(deg_l, nullptr, n_l * es);
     r.xblocks = (int32_t)xblocks;
     r.zblocks = (int32_t)zblocks;
@@ -788,6 +814,9 @@ struct Engine : EngineBase {
                                         : FS_ALL;
     }
     n_b = (int64_t)P.var_b.size();
+    w_stride = P.w_stride;
+    w_base = P.w_base;
+    l_base = P.l_base;
     n_w = (int64_t)P.var_w.size();
     n_l = (int64_t)P.var_l.size();
     nb_w = (n_w + ZPB - 1) / ZPB;
@@ -813,7 +842,6 @@ struct Engine : EngineBase {
     if ((s = put(&var_w, P.var_w))) return s;
     if ((s = put(&var_l, P.var_l))) return s;
     if ((s = put(&rng_w, P.rng_w))) return s;
-    if ((s = put(&rng_l, P.rng_l))) return s;
     if ((s = put_conv(&deg_w, P.deg_w))) return s;
     if ((s = put_conv(&deg_l, P.deg_l))) return s;
     if ((s = put(&upos, P.upos))) return s;
@@ -901,9 +929,11 @@ struct Engine : EngineBase {
     a.n_w = n_w;
     a.nb_w = (int32_t)nb_w;
     a.var_l = var_l;
-    a.rng_l = rng_l;
     a.deg_l = deg_l;
     a.n_l = n_l;
+    a.w_stride = w_stride;
+    a.w_base = w_base;
+    a.l_base = l_base;
     a.zin = z[zc];
     a.zout = z[zc ^ 1];
     a.blockmax = bmz;

@@ -85,14 +85,14 @@ struct ZArgs {
   const T* deg_b;
   int32_t n_b;
   const int32_t* var_w;   // lists of LANE_MAX+1 .. ZB_MIN: one 16-lane row each
-  const int64_t* rng_w;
+  const int64_t* rng_w;   // explicit ranges when w_stride == 0
   const T* deg_w;
   int64_t n_w;
   int32_t nb_w;
-  const int32_t* var_l;
-  const int64_t* rng_l;
-  const T* deg_l;
+  const int32_t* var_l;   // lists of at most LANE_MAX: one lane each, stride LANE_MAX
+  const T* deg_l;         // 0: no edge, z keeps its value
   int64_t n_l;
+  int64_t w_stride, w_base, l_base;  // padded list layout (pool positions)
   const T* zin;
   T* zout;
   T* blockmax;
@@ -1176,8 +1176,13 @@ __device__ __forceinline__ void zpass_block(ZArgs<T> a, int blk) {
     const bool ok = k < a.n_w;
     T s = T(0);
     if (ok) {
-      const int64_t o1 = a.rng_w[2 * k + 1];
-      for (int64_t j = a.rng_w[2 * k] + sl; j < o1; j += ZSEG) s += a.pool[j];
+      if (a.w_stride) {
+        const T* p = a.pool + a.w_base + k * a.w_stride;
+        for (int64_t j = sl; j < a.w_stride; j += ZSEG) s += p[j];
+      } else {
+        const int64_t o1 = a.rng_w[2 * k + 1];
+        for (int64_t j = a.rng_w[2 * k] + sl; j < o1; j += ZSEG) s += a.pool[j];
+      }
     }
     s = admmi::row16_sum(s);
     if (ok && sl == 0) {
@@ -1190,13 +1195,13 @@ __device__ __forceinline__ void zpass_block(ZArgs<T> a, int blk) {
     const int64_t k = (int64_t)(blk - a.n_b - a.nb_w) * NT + threadIdx.x;
     if (k < a.n_l) {
       const int zi = a.var_l[k];
-      const int64_t o0 = a.rng_l[2 * k], o1 = a.rng_l[2 * k + 1];
+      const T d = a.deg_l[k];
+      const T* p = a.pool + a.l_base + k * LANE_MAX;
+      T s = p[0];
+#pragma unroll
+      for (int j = 1; j < LANE_MAX; ++j) s += p[j];
       T zn = a.zin[zi];
-      if (o1 > o0) {
-        T s = T(0);
-        for (int64_t j = o0; j < o1; ++j) s += a.pool[j];
-        zn = s / a.deg_l[k];
-      }
+      if (d > T(0)) zn = s / d;
       a.zout[zi] = zn;
       if (a.check) dmax = tabs(zn - a.zin[zi]);
     }
@@ -1233,7 +1238,7 @@ struct ResArgs {
   ResRegion reg[RES_MAX_REG];
   int32_t nreg;
   int32_t o_pool, o_par, o_idx, o_z0, o_z1;
-  int32_t o_var_b, o_rng_b, o_deg_b, o_var_w, o_rng_w, o_deg_w, o_var_l, o_rng_l, o_deg_l;
+  int32_t o_var_b, o_rng_b, o_deg_b, o_var_w, o_rng_w, o_deg_w, o_var_l, o_deg_l;
   int32_t zc, iters, xblocks, zblocks, z_words;
   T* z_back[2];     // global z buffers (the final z is copied to z_back[final index])
 };
@@ -1258,7 +1263,6 @@ __global__ __launch_bounds__(NT) void resident_kernel(XArgs<T> xa, ZArgs<T> za, 
   za.rng_w = (const int64_t*)(lds_img + r.o_rng_w);
   za.deg_w = (const T*)(lds_img + r.o_deg_w);
   za.var_l = (const int32_t*)(lds_img + r.o_var_l);
-  za.rng_l = (const int64_t*)(lds_img + r.o_rng_l);
   za.deg_l = (const T*)(lds_img + r.o_deg_l);
   // z buffers are addressed as lds_img + offset each iteration (not through a
   // pointer carried across iterations) so that every z access stays an LDS
