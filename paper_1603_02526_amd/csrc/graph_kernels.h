@@ -137,19 +137,26 @@ __device__ __forceinline__ void state_un(T m, T xo, T zv, T alpha, T& u, T& n) {
 // Proximal operators in working precision (appendix closed forms).
 // ---------------------------------------------------------------------------
 
+// Square root and reciprocal: FP32 uses the hardware instructions (within
+// 1 ulp), FP64 the correctly rounded library forms.
+__device__ __forceinline__ float tsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ double tsqrt(double x) { return sqrt(x); }
+__device__ __forceinline__ float trcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double trcp(double x) { return 1.0 / x; }
+
 // Non-overlap |c1 - c2| >= r1 + r2 with equal weights: move both centres
 // apart along n_hat and shrink both radii by D/4, D = max(0, r1+r2-|c2-c1|);
 // n_hat = (1,0) when the centres coincide.
 template <typename T>
 __device__ __forceinline__ bool prox_nonoverlap(T* v) {
   const T dx = v[3] - v[0], dy = v[4] - v[1];
-  const T L = sqrt(dx * dx + dy * dy);
+  const T L = tsqrt(dx * dx + dy * dy);
   const T D = v[2] + v[5] - L;
   const bool moved = D > T(0);
   if (moved) {
     T hx = T(1), hy = T(0);
     if (L > T(0)) {
-      const T il = T(1) / L;
+      const T il = trcp(L);
       hx = dx * il;
       hy = dy * il;
     }

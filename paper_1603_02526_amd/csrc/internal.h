@@ -51,6 +51,19 @@ __device__ __forceinline__ float wave_sum(float v) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
 }
 
+// Max over the wavefront of non-negative values, DPP only (lanes a row
+// mask leaves out read 0, which cannot exceed the max); every lane returns
+// the result.  Every lane of the wavefront must be active at the call.
+__device__ __forceinline__ float wave_max_nonneg(float v) {
+  v = fmaxf(v, ADMM_DPP(v, 0xB1, 0xF));   // pairs
+  v = fmaxf(v, ADMM_DPP(v, 0x4E, 0xF));   // quads
+  v = fmaxf(v, ADMM_DPP(v, 0x141, 0xF));  // 8 lanes
+  v = fmaxf(v, ADMM_DPP(v, 0x140, 0xF));  // 16 lanes
+  v = fmaxf(v, ADMM_DPP(v, 0x142, 0xA));  // row_bcast:15 into rows 1 and 3
+  v = fmaxf(v, ADMM_DPP(v, 0x143, 0xC));  // row_bcast:31 into rows 2 and 3
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+
 // Sum over each 16-lane row (DPP row), result in every lane of the row.
 __device__ __forceinline__ float row16_sum(float v) {
   v += ADMM_DPP(v, 0xB1, 0xF);   // pairs

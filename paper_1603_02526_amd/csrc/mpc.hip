@@ -49,15 +49,19 @@ struct MpcInst {
 //   rho/(rho+r), q [N], r [4], lo, hi
 // Padded components of z and m stay exactly zero through every update.
 struct ParOff {
-  int M, S, B, S0, A, cq, cr, q, r, lo, size;
+  int N4, K4;  // N rounded up to 4; row width of M
+  int M, MT, S, S0, B, A, cq, cr, q, r, lo, size;
 };
 __host__ __device__ constexpr ParOff par_offsets(int N) {
   ParOff o{};
-  o.M = 0;
-  o.S = o.M + N * (N + MM);
-  o.B = o.S + N * N;
-  o.S0 = o.B + N * MM;
-  o.A = o.S0 + N * N;
+  o.N4 = (N + 3) / 4 * 4;
+  o.K4 = o.N4 + MM;
+  o.M = 0;                         // [N][K4]: A row | 0 .. | B row
+  o.MT = o.M + N * o.K4;           // [K4][N4]: column j of [A 0 B], zero padded
+  o.S = o.MT + o.K4 * o.N4;        // [N][N4]
+  o.S0 = o.S + N * o.N4;           // [N][N4]
+  o.B = o.S0 + N * o.N4;           // [N][MM]
+  o.A = o.B + N * MM;              // [N][N]
   o.cq = o.A + N * N;
   o.cr = o.cq + N;
   o.q = o.cr + MM;
@@ -68,6 +72,7 @@ __host__ __device__ constexpr ParOff par_offsets(int N) {
 }
 __host__ __device__ constexpr int pad_n(int n) { return n < 4 ? 4 : n; }
 constexpr int PBLK = par_offsets(MN).size + MN;  // parameter block + c = A x0 (floats)
+static_assert(PBLK % 4 == 0, "parameter slots must stay 16-byte aligned");
 
 struct SolveArgs {
   const MpcInst* inst;
@@ -97,6 +102,35 @@ __device__ __forceinline__ void isync() {
 }
 
 __device__ __forceinline__ float fabsf_(float v) { return v < 0.f ? -v : v; }
+
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+// out[i] += sum_c P[i*C + c] x[c] for i < R, P in LDS with 16-byte aligned
+// rows of C floats (C % 4 == 0), terms added in c order.  Row i+1 is read
+// while row i is summed; the scheduling barrier per row keeps the compiler
+// from reading every row ahead (the whole block would not fit in registers).
+template <int R, int C>
+__device__ __forceinline__ void mv_rows(const float* P, const float (&x)[C], float (&out)[R]) {
+  f4v cur[C / 4], nxt[C / 4];
+#pragma unroll
+  for (int q = 0; q < C / 4; ++q) cur[q] = ((const f4v*)P)[q];
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    if (i + 1 < R) {
+#pragma unroll
+      for (int q = 0; q < C / 4; ++q) nxt[q] = ((const f4v*)(P + (i + 1) * C))[q];
+    }
+    float s = out[i];
+#pragma unroll
+    for (int q = 0; q < C / 4; ++q)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) s = fmaf(cur[q][e], x[4 * q + e], s);
+    out[i] = s;
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int q = 0; q < C / 4; ++q) cur[q] = nxt[q];
+  }
+}
 __device__ __forceinline__ float fmaxf_(float a, float b) { return a > b ? a : b; }
 
 // One instance.  LOCK: all four wavefronts of the workgroup work on it in
@@ -106,7 +140,6 @@ __device__ __forceinline__ float fmaxf_(float a, float b) { return a > b ? a : b
 template <bool LOCK, int N>
 __device__ __forceinline__ void solve_one(const SolveArgs a, int id, int t, int xb, float* xz,
                                           float* xm, float* red, float* ps) {
-  constexpr int K = N + MM;
   constexpr ParOff o = par_offsets(N);
   const MpcInst I = a.inst[id];
   const int T = __builtin_amdgcn_readfirstlane(I.T);
@@ -225,54 +258,30 @@ __device__ __forceinline__ void solve_one(const SolveArgs a, int id, int t, int 
 #pragma unroll
       for (int i = 0; i < N; ++i) bv[i] = 2.f * zx1[i] - mdx1[i];
       // dynamics: w = M a + c - b; v = S w (S0 at t = 0); a -= M^T v; b += v
-      float wv[N], vv[N];
+      constexpr int N4 = o.N4, K4 = o.K4;
+      float xa[K4], wv[N], wp[N4], vv[N], vp[N4], sx[N], su[MM];
 #pragma unroll
-      for (int i = 0; i < N; ++i) {
-        float s = cvec[i] - bv[i];
+      for (int c = 0; c < K4; ++c) xa[c] = c < N ? ax[c < N ? c : 0] : (c >= N4 ? au[c >= N4 ? c - N4 : 0] : 0.f);
 #pragma unroll
-        for (int j = 0; j < N; ++j) s += P[o.M + i * K + j] * ax[j];
+      for (int i = 0; i < N; ++i) wv[i] = cvec[i] - bv[i];
+      mv_rows<N, K4>(P + o.M, xa, wv);
 #pragma unroll
-        for (int j = 0; j < MM; ++j) s += P[o.M + i * K + N + j] * au[j];
-        wv[i] = s;
-        __builtin_amdgcn_sched_barrier(0);
-      }
-      const int so = (t >= 1) ? o.S : o.S0;
-      if (t >= 1) {
+      for (int c = 0; c < N4; ++c) wp[c] = c < N ? wv[c < N ? c : 0] : 0.f;
 #pragma unroll
-        for (int i = 0; i < N; ++i) {
-          float s = 0.f;
+      for (int i = 0; i < N; ++i) vv[i] = 0.f;
+      mv_rows<N, N4>(P + ((t >= 1) ? o.S : o.S0), wp, vv);
 #pragma unroll
-          for (int j = 0; j < N; ++j) s += P[o.S + i * N + j] * wv[j];
-          vv[i] = s;
-          __builtin_amdgcn_sched_barrier(0);
-        }
-      } else {
+      for (int c = 0; c < N4; ++c) vp[c] = c < N ? vv[c < N ? c : 0] : 0.f;
 #pragma unroll
-        for (int i = 0; i < N; ++i) {
-          float s = 0.f;
+      for (int i = 0; i < N; ++i) sx[i] = 0.f;
 #pragma unroll
-          for (int j = 0; j < N; ++j) s += P[o.S0 + i * N + j] * wv[j];
-          vv[i] = s;
-          __builtin_amdgcn_sched_barrier(0);
-        }
-      }
-      (void)so;
+      for (int j = 0; j < MM; ++j) su[j] = 0.f;
+      mv_rows<N, N4>(P + o.MT, vp, sx);
+      mv_rows<MM, N4>(P + o.MT + N4 * N4, vp, su);
 #pragma unroll
-      for (int j = 0; j < N; ++j) {
-        float s = 0.f;
+      for (int j = 0; j < N; ++j) ax[j] -= sx[j];
 #pragma unroll
-        for (int i = 0; i < N; ++i) s += P[o.M + i * K + j] * vv[i];
-        ax[j] -= s;
-        __builtin_amdgcn_sched_barrier(0);
-      }
-#pragma unroll
-      for (int j = 0; j < MM; ++j) {
-        float s = 0.f;
-#pragma unroll
-        for (int i = 0; i < N; ++i) s += P[o.M + i * K + N + j] * vv[i];
-        au[j] -= s;
-        __builtin_amdgcn_sched_barrier(0);
-      }
+      for (int j = 0; j < MM; ++j) au[j] -= su[j];
 #pragma unroll
       for (int i = 0; i < N; ++i) bv[i] += vv[i];
       // separable costs and the box
@@ -311,7 +320,7 @@ __device__ __forceinline__ void solve_one(const SolveArgs a, int id, int t, int 
       for (int i = 0; i < N; ++i) {
         float s = mdx1[i] + mqx[i];
         if (nxt) s += xm[(xb + t + 1) * MN + i];
-        const float zn = s / (nxt ? 3.f : 2.f);
+        const float zn = s * (nxt ? (1.f / 3.f) : 0.5f);
         sloc = fmaxf_(sloc, fabsf_(zn - zx1[i]));
         rloc = fmaxf_(rloc, fmaxf_(fabsf_(bv[i] - zn), fabsf_(xqx[i] - zn)));
         zx1n[i] = zn;
@@ -320,7 +329,7 @@ __device__ __forceinline__ void solve_one(const SolveArgs a, int id, int t, int 
 #pragma unroll
       for (int j = 0; j < MM; ++j) {
         const float s = box ? (mdu[j] + mqu[j] + mbx[j]) : (mdu[j] + mqu[j]);
-        const float zn = s / (box ? 3.f : 2.f);
+        const float zn = s * (box ? (1.f / 3.f) : 0.5f);
         sloc = fmaxf_(sloc, fabsf_(zn - zu[j]));
         float r = fmaxf_(fabsf_(au[j] - zn), fabsf_(xqu[j] - zn));
         if (box) r = fmaxf_(r, fabsf_(xbx[j] - zn));
@@ -340,7 +349,7 @@ __device__ __forceinline__ void solve_one(const SolveArgs a, int id, int t, int 
       }
     }
     // ---- stopping rule, reduced over the instance
-    float r = admmi::wave_max(rloc), s = admmi::wave_max(sloc);
+    float r = admmi::wave_max_nonneg(rloc), s = admmi::wave_max_nonneg(sloc);
     if constexpr (LOCK) {
       if ((threadIdx.x & 63) == 0) { red[2 * w] = r; red[2 * w + 1] = s; }
       __syncthreads();
@@ -403,7 +412,7 @@ __global__ __launch_bounds__(WGT) void mpc_solve_kernel(
   __shared__ float xz[TMAX * MN];
   __shared__ float xm[TMAX * MN];
   __shared__ float red[8];
-  __shared__ float ps[4 * PBLK];
+  __shared__ __align__(16) float ps[4 * PBLK];   // rows read as 16-byte vectors
   __shared__ int s_item;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   for (;;) {
@@ -657,12 +666,18 @@ admm_status admm_mpc_batch_create(int32_t n_inst, const int32_t* T, const int32_
     boff += ni * mi;
     qoff += ni;
     roff += mi;
-    const int Np = pad_n(ni), Kp = Np + MM;
+    const int Np = pad_n(ni);
     const ParOff o = par_offsets(Np);
     std::vector<double> blk(o.size, 0.0);
     for (int rr = 0; rr < ni; ++rr) {
-      for (int j = 0; j < ni; ++j) blk[o.M + rr * Kp + j] = Ai[rr * ni + j];
-      for (int j = 0; j < mi; ++j) blk[o.M + rr * Kp + Np + j] = Bi[rr * mi + j];
+      for (int j = 0; j < ni; ++j) {
+        blk[o.M + rr * o.K4 + j] = Ai[rr * ni + j];
+        blk[o.MT + j * o.N4 + rr] = Ai[rr * ni + j];
+      }
+      for (int j = 0; j < mi; ++j) {
+        blk[o.M + rr * o.K4 + o.N4 + j] = Bi[rr * mi + j];
+        blk[o.MT + (o.N4 + j) * o.N4 + rr] = Bi[rr * mi + j];
+      }
     }
     std::vector<double> G(ni * ni, 0.0), G0(ni * ni, 0.0);
     for (int a1 = 0; a1 < ni; ++a1)
@@ -679,8 +694,8 @@ admm_status admm_mpc_batch_create(int32_t n_inst, const int32_t* T, const int32_
     std::vector<double> S = inv_spd(G, ni), S0 = inv_spd(G0, ni);
     for (int a1 = 0; a1 < ni; ++a1)
       for (int a2 = 0; a2 < ni; ++a2) {
-        blk[o.S + a1 * Np + a2] = S[a1 * ni + a2];
-        blk[o.S0 + a1 * Np + a2] = S0[a1 * ni + a2];
+        blk[o.S + a1 * o.N4 + a2] = S[a1 * ni + a2];
+        blk[o.S0 + a1 * o.N4 + a2] = S0[a1 * ni + a2];
         blk[o.A + a1 * Np + a2] = Ai[a1 * ni + a2];
       }
     for (int a1 = 0; a1 < ni; ++a1)
