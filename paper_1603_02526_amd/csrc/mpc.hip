@@ -101,9 +101,18 @@ __device__ __forceinline__ void isync() {
   }
 }
 
-__device__ __forceinline__ float fabsf_(float v) { return v < 0.f ? -v : v; }
 
 typedef float f4v __attribute__((ext_vector_type(4)));
+
+// Whole-wavefront shifts by one lane (DPP wave_shr:1 / wave_shl:1): lane t
+// receives lane t-1's (resp. t+1's) value; lane 0 (resp. 63) receives 0.
+// Every lane of the wavefront must be active.
+__device__ __forceinline__ float lane_prev(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float lane_next(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xF, 0xF, false));
+}
 
 // out[i] += sum_c P[i*C + c] x[c] for i < R, P in LDS with 16-byte aligned
 // rows of C floats (C % 4 == 0), terms added in c order.  Row i+1 is read
@@ -131,7 +140,6 @@ __device__ __forceinline__ void mv_rows(const float* P, const float (&x)[C], flo
     for (int q = 0; q < C / 4; ++q) cur[q] = nxt[q];
   }
 }
-__device__ __forceinline__ float fmaxf_(float a, float b) { return a > b ? a : b; }
 
 // One instance.  LOCK: all four wavefronts of the workgroup work on it in
 // lockstep (t = threadIdx.x); otherwise this wavefront alone (t = lane).
@@ -176,15 +184,26 @@ __device__ __forceinline__ void solve_one(const SolveArgs a, int id, int t, int 
 #pragma unroll
     for (int i = 0; i < N; ++i) if (i < n) zx1[i] = zi[m + i];
   }
-  if (act) {
+  // z of x_t, the previous step's x_{t+1} (0 at t = 0).  One wavefront per
+  // instance exchanges neighbours by lane shifts; lockstep wavefronts
+  // through LDS.  The same value is carried across iterations in zxpc.
+  float zxpc[N];
+  if constexpr (LOCK) {
+    if (act) {
 #pragma unroll
-    for (int i = 0; i < N; ++i) xz[(xb + t) * MN + i] = zx1[i];
+      for (int i = 0; i < N; ++i) xz[(xb + t) * MN + i] = zx1[i];
+    }
+    isync<LOCK>();
+#pragma unroll
+    for (int i = 0; i < N; ++i) zxpc[i] = (act && t >= 1) ? xz[(xb + t - 1) * MN + i] : 0.f;
+  } else {
+#pragma unroll
+    for (int i = 0; i < N; ++i) zxpc[i] = lane_prev(zx1[i]);
   }
-  isync<LOCK>();
   if (act) {
     float zxp[N];
 #pragma unroll
-    for (int i = 0; i < N; ++i) zxp[i] = (t >= 1) ? xz[(xb + t - 1) * MN + i] : 0.f;
+    for (int i = 0; i < N; ++i) zxp[i] = zxpc[i];
     // m = u + z per edge; u per step laid out [dx n | du m | dx1 n | qu m | bx m | qx n]
     if (a.uinit) {
       const float* ui = a.uinit + I.u_off + (int64_t)t * 3 * k;
@@ -247,9 +266,14 @@ __device__ __forceinline__ void solve_one(const SolveArgs a, int id, int t, int 
     asm volatile("s_mov_b32 %0, 0" : "=s"(zoff));
     const float* P = Pb + zoff;
     float zxp[N];
-    if (act) {
+    if constexpr (LOCK) {
 #pragma unroll
-      for (int i = 0; i < N; ++i) zxp[i] = (t >= 1) ? xz[(xb + t - 1) * MN + i] : 0.f;
+      for (int i = 0; i < N; ++i) zxp[i] = (act && t >= 1) ? xz[(xb + t - 1) * MN + i] : 0.f;
+    } else {
+#pragma unroll
+      for (int i = 0; i < N; ++i) zxp[i] = zxpc[i];
+    }
+    if (act) {
       // ---- x-update.  n = z - u = 2z - m on every edge.
 #pragma unroll
       for (int i = 0; i < N; ++i) ax[i] = (t >= 1) ? (2.f * zxp[i] - mdx[i]) : 0.f;
@@ -306,48 +330,73 @@ __device__ __forceinline__ void solve_one(const SolveArgs a, int id, int t, int 
         mqu[j] = xqu[j] + (mqu[j] - zu[j]);
         mbx[j] = xbx[j] + (mbx[j] - zu[j]);
       }
-      if (t >= 1) {
+      if constexpr (LOCK) {
+        if (t >= 1) {
 #pragma unroll
-        for (int i = 0; i < N; ++i) xm[(xb + t) * MN + i] = mdx[i];
+          for (int i = 0; i < N; ++i) xm[(xb + t) * MN + i] = mdx[i];
+        }
       }
     }
-    isync<LOCK>();
+    // m of the next step's dynamics edge on x_{t+1}
+    float xmn[N];
+    if constexpr (LOCK) {
+      isync<LOCK>();
+#pragma unroll
+      for (int i = 0; i < N; ++i) xmn[i] = (act && t + 1 < T) ? xm[(xb + t + 1) * MN + i] : 0.f;
+    } else {
+#pragma unroll
+      for (int i = 0; i < N; ++i) xmn[i] = lane_next(mdx[i]);
+    }
     float zx1n[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) zx1n[i] = 0.f;
+    // residual maxima use v_max (which drops NaN): a NaN in this step's new
+    // z makes chk NaN, and the step then reports an infinite residual
+    float chk = 0.f;
     if (act) {
       // ---- z-update: 3-term averages (x_T and box-free inputs: 2 terms)
       const bool nxt = (t + 1 < T);
 #pragma unroll
       for (int i = 0; i < N; ++i) {
         float s = mdx1[i] + mqx[i];
-        if (nxt) s += xm[(xb + t + 1) * MN + i];
+        if (nxt) s += xmn[i];
         const float zn = s * (nxt ? (1.f / 3.f) : 0.5f);
-        sloc = fmaxf_(sloc, fabsf_(zn - zx1[i]));
-        rloc = fmaxf_(rloc, fmaxf_(fabsf_(bv[i] - zn), fabsf_(xqx[i] - zn)));
+        sloc = fmaxf(sloc, fabsf(zn - zx1[i]));
+        rloc = fmaxf(rloc, fmaxf(fabsf(bv[i] - zn), fabsf(xqx[i] - zn)));
         zx1n[i] = zn;
-        xz[(xb + t) * MN + i] = zn;
+        chk += zn;
+        if constexpr (LOCK) xz[(xb + t) * MN + i] = zn;
       }
 #pragma unroll
       for (int j = 0; j < MM; ++j) {
         const float s = box ? (mdu[j] + mqu[j] + mbx[j]) : (mdu[j] + mqu[j]);
         const float zn = s * (box ? (1.f / 3.f) : 0.5f);
-        sloc = fmaxf_(sloc, fabsf_(zn - zu[j]));
-        float r = fmaxf_(fabsf_(au[j] - zn), fabsf_(xqu[j] - zn));
-        if (box) r = fmaxf_(r, fabsf_(xbx[j] - zn));
-        rloc = fmaxf_(rloc, r);
+        sloc = fmaxf(sloc, fabsf(zn - zu[j]));
+        float r = fmaxf(fabsf(au[j] - zn), fabsf(xqu[j] - zn));
+        if (box) r = fmaxf(r, fabsf(xbx[j] - zn));
+        rloc = fmaxf(rloc, r);
+        chk += zn;
         zu[j] = zn;
       }
     }
-    isync<LOCK>();
+    // the previous step's new z of x_t: residual of this step's x_t edge
+    // and, next iteration, its z of x_t
+    if constexpr (LOCK) {
+      isync<LOCK>();
+#pragma unroll
+      for (int i = 0; i < N; ++i) zxpc[i] = (act && t >= 1) ? xz[(xb + t - 1) * MN + i] : 0.f;
+    } else {
+#pragma unroll
+      for (int i = 0; i < N; ++i) zxpc[i] = lane_prev(zx1n[i]);
+    }
     if (act) {
 #pragma unroll
       for (int i = 0; i < N; ++i) {
         zx1[i] = zx1n[i];
-        if (t >= 1) {
-          const float zp = xz[(xb + t - 1) * MN + i];
-          rloc = fmaxf_(rloc, fabsf_(ax[i] - zp));
-        }
+        if (t >= 1) rloc = fmaxf(rloc, fabsf(ax[i] - zxpc[i]));
       }
     }
+    if (!(chk == chk)) rloc = __builtin_inff();
     // ---- stopping rule, reduced over the instance
     float r = admmi::wave_max_nonneg(rloc), s = admmi::wave_max_nonneg(sloc);
     if constexpr (LOCK) {
@@ -355,7 +404,7 @@ __device__ __forceinline__ void solve_one(const SolveArgs a, int id, int t, int 
       __syncthreads();
       r = red[0];
       s = red[1];
-      for (int q = 1; q < nw; ++q) { r = fmaxf_(r, red[2 * q]); s = fmaxf_(s, red[2 * q + 1]); }
+      for (int q = 1; q < nw; ++q) { r = fmaxf(r, red[2 * q]); s = fmaxf(s, red[2 * q + 1]); }
     }
     s *= a.rho;
     if (r <= a.tol && s <= a.tol) {

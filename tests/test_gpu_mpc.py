@@ -156,3 +156,32 @@ def test_max_iter_reported_negative():
     b = M.MPCBatch(insts)
     z, it = _solve(b, insts, tol=1e-4, max_iter=3)
     assert np.all(it == -3)
+
+
+def test_nan_instance_is_reported_unconverged():
+    """A NaN in one instance's x0 (one wavefront, and one of the lockstep
+    instances) never meets the stopping rule: its count is -max_iter, and
+    the other instances' results are those of a batch without it."""
+    M = _mpc()
+    insts = _edge_instances()[:6]
+    bad = [1, 4]                      # T = 2 (one wavefront) and T = 65 (two lockstep)
+    x0s = [i.x0.copy() for i in insts]
+    for b in bad:
+        x0s[b][0] = np.nan
+    batch = M.MPCBatch(insts)
+    x0 = torch.tensor(batch.pack_x0(x0s), device="cuda")
+    z = torch.zeros(batch.z_total, dtype=torch.float32, device="cuda")
+    it = torch.zeros(batch.n_inst, dtype=torch.int32, device="cuda")
+    batch.solve(x0, z, it, tol=1e-4, max_iter=300)
+    torch.cuda.synchronize()
+    it = it.cpu().numpy()
+    assert all(it[b] == -300 for b in bad)
+    ref_z, ref_it = _solve(batch, insts, 1e-4, 300)
+    zz = z.cpu().numpy()
+    assert any(ref_it[k] > 0 for k in range(len(insts)) if k not in bad)
+    for k in range(len(insts)):
+        if k in bad:
+            continue
+        assert it[k] == ref_it[k]
+        sl = batch.split_z(zz)[k]
+        np.testing.assert_array_equal(sl, batch.split_z(ref_z.astype(np.float32))[k])
