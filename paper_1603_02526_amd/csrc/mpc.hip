@@ -266,13 +266,8 @@ __device__ __forceinline__ void solve_one(const SolveArgs a, int id, int t, int 
     asm volatile("s_mov_b32 %0, 0" : "=s"(zoff));
     const float* P = Pb + zoff;
     float zxp[N];
-    if constexpr (LOCK) {
 #pragma unroll
-      for (int i = 0; i < N; ++i) zxp[i] = (act && t >= 1) ? xz[(xb + t - 1) * MN + i] : 0.f;
-    } else {
-#pragma unroll
-      for (int i = 0; i < N; ++i) zxp[i] = zxpc[i];
-    }
+    for (int i = 0; i < N; ++i) zxp[i] = zxpc[i];
     if (act) {
       // ---- x-update.  n = z - u = 2z - m on every edge.
 #pragma unroll
@@ -330,22 +325,32 @@ __device__ __forceinline__ void solve_one(const SolveArgs a, int id, int t, int 
         mqu[j] = xqu[j] + (mqu[j] - zu[j]);
         mbx[j] = xbx[j] + (mbx[j] - zu[j]);
       }
-      if constexpr (LOCK) {
-        if (t >= 1) {
+    }
+    // From step t+1 (lane t+1): the m and the x of its dynamics edge on
+    // x_{t+1}.  Lane shifts inside a wavefront; in lockstep mode lane 63
+    // takes them from the next wavefront's lane 0 through LDS.
+    float xmn[N], axn[N];
 #pragma unroll
-          for (int i = 0; i < N; ++i) xm[(xb + t) * MN + i] = mdx[i];
+    for (int i = 0; i < N; ++i) {
+      xmn[i] = lane_next(mdx[i]);
+      axn[i] = lane_next(ax[i]);
+    }
+    if constexpr (LOCK) {
+      if ((t & 63) == 0) {
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+          xm[w * 2 * MN + i] = mdx[i];
+          xm[w * 2 * MN + MN + i] = ax[i];
         }
       }
-    }
-    // m of the next step's dynamics edge on x_{t+1}
-    float xmn[N];
-    if constexpr (LOCK) {
-      isync<LOCK>();
+      __syncthreads();
+      if ((t & 63) == 63 && w + 1 < nw) {
 #pragma unroll
-      for (int i = 0; i < N; ++i) xmn[i] = (act && t + 1 < T) ? xm[(xb + t + 1) * MN + i] : 0.f;
-    } else {
-#pragma unroll
-      for (int i = 0; i < N; ++i) xmn[i] = lane_next(mdx[i]);
+        for (int i = 0; i < N; ++i) {
+          xmn[i] = xm[(w + 1) * 2 * MN + i];
+          axn[i] = xm[(w + 1) * 2 * MN + MN + i];
+        }
+      }
     }
     float zx1n[N];
 #pragma unroll
@@ -354,7 +359,9 @@ __device__ __forceinline__ void solve_one(const SolveArgs a, int id, int t, int 
     // z makes chk NaN, and the step then reports an infinite residual
     float chk = 0.f;
     if (act) {
-      // ---- z-update: 3-term averages (x_T and box-free inputs: 2 terms)
+      // ---- z-update: 3-term averages (x_T and box-free inputs: 2 terms).
+      // The residual of step t+1's dynamics edge on x_{t+1} is taken here,
+      // where the new z of x_{t+1} is.
       const bool nxt = (t + 1 < T);
 #pragma unroll
       for (int i = 0; i < N; ++i) {
@@ -363,9 +370,9 @@ __device__ __forceinline__ void solve_one(const SolveArgs a, int id, int t, int 
         const float zn = s * (nxt ? (1.f / 3.f) : 0.5f);
         sloc = fmaxf(sloc, fabsf(zn - zx1[i]));
         rloc = fmaxf(rloc, fmaxf(fabsf(bv[i] - zn), fabsf(xqx[i] - zn)));
+        if (nxt) rloc = fmaxf(rloc, fabsf(axn[i] - zn));
         zx1n[i] = zn;
         chk += zn;
-        if constexpr (LOCK) xz[(xb + t) * MN + i] = zn;
       }
 #pragma unroll
       for (int j = 0; j < MM; ++j) {
@@ -378,22 +385,18 @@ __device__ __forceinline__ void solve_one(const SolveArgs a, int id, int t, int 
         chk += zn;
         zu[j] = zn;
       }
+#pragma unroll
+      for (int i = 0; i < N; ++i) zx1[i] = zx1n[i];
     }
-    // the previous step's new z of x_t: residual of this step's x_t edge
-    // and, next iteration, its z of x_t
+    // next iteration's z of x_t: the new z of step t-1 (lane t-1); in
+    // lockstep mode lane 0 takes it from the previous wavefront's lane 63
+    // through LDS, across the barrier of the stopping-rule reduction
+#pragma unroll
+    for (int i = 0; i < N; ++i) zxpc[i] = lane_prev(zx1n[i]);
     if constexpr (LOCK) {
-      isync<LOCK>();
+      if ((t & 63) == 63) {
 #pragma unroll
-      for (int i = 0; i < N; ++i) zxpc[i] = (act && t >= 1) ? xz[(xb + t - 1) * MN + i] : 0.f;
-    } else {
-#pragma unroll
-      for (int i = 0; i < N; ++i) zxpc[i] = lane_prev(zx1n[i]);
-    }
-    if (act) {
-#pragma unroll
-      for (int i = 0; i < N; ++i) {
-        zx1[i] = zx1n[i];
-        if (t >= 1) rloc = fmaxf(rloc, fabsf(ax[i] - zxpc[i]));
+        for (int i = 0; i < N; ++i) xz[w * MN + i] = zx1n[i];
       }
     }
     if (!(chk == chk)) rloc = __builtin_inff();
@@ -405,6 +408,10 @@ __device__ __forceinline__ void solve_one(const SolveArgs a, int id, int t, int 
       r = red[0];
       s = red[1];
       for (int q = 1; q < nw; ++q) { r = fmaxf(r, red[2 * q]); s = fmaxf(s, red[2 * q + 1]); }
+      if ((t & 63) == 0 && w >= 1) {
+#pragma unroll
+        for (int i = 0; i < N; ++i) zxpc[i] = xz[(w - 1) * MN + i];
+      }
     }
     s *= a.rho;
     if (r <= a.tol && s <= a.tol) {
