@@ -248,16 +248,22 @@ admm_status admm_mpc_batch_dual_complete(admm_mpc_batch* b, const float* z, floa
                                          void* stream);
 
 /* Schedule of the persistent launch: pack1 = instances per workgroup for
- * T <= 64 (1, 2 or 4), order (0 as given, 1 most work first, 2 grouped by
- * (n, m)), grid = workgroups (0: as many as fit on the device at once).
- * Results do not depend on the plan (bitwise). */
+ * T <= 64 (1, 2 or 4), order (0 as given, 1 most work per iteration first,
+ * 2 grouped by (n, m), 3 longest expected solve first: the iteration counts
+ * of the autotuner's cold solve times the latency of one iteration; as 1
+ * before a tuning run), grid = workgroups (0: as many as fit on the device
+ * at once).  A batch finishes with its slowest instance, so starting the
+ * longest solves first shortens it.  Results do not depend on the plan
+ * (bitwise). */
 admm_status admm_mpc_batch_set_plan(admm_mpc_batch* b, int32_t pack1, int32_t order,
                                     int32_t grid);
 admm_status admm_mpc_batch_get_plan(const admm_mpc_batch* b, int32_t* pack1,
                                     int32_t* order, int32_t* grid, int32_t* resident);
 
-/* Autotuner: time every candidate plan on cold solves of this batch from x0
- * (device), reps launches each (best time kept), then keep the fastest.
+/* Autotuner: one cold solve of this batch from x0 (device) records each
+ * instance's iterations (for order 3), then every candidate plan is timed
+ * on cold solves, reps launches each (best time kept), and the fastest is
+ * kept.
  * z_scratch [z_total] and iters_scratch [n_inst] are device work arrays;
  * times_ms [max_candidates] (host, nullable) receives each candidate's time.
  * Synchronises the stream. */

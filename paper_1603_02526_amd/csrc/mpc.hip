@@ -563,7 +563,8 @@ std::vector<double> inv_spd(std::vector<double> a, int n) {
 
 struct Plan {
   int pack1 = 4;  // instances per workgroup when T <= 64
-  int order = 1;  // 0 as given, 1 longest first, 2 by (n, m) then longest first
+  int order = 1;  // 0 as given, 1 longest first, 2 by (n, m) then longest first,
+                  // 3 longest measured solve first (iterations of the last tuning solve)
   int grid = 0;   // persistent workgroups; 0: resident capacity
 };
 
@@ -583,6 +584,7 @@ struct admm_mpc_batch {
   int32_t* d_counter = nullptr;
   Plan plan;
   int resident = 0;          // workgroups resident per device at full occupancy
+  std::vector<int32_t> measured;  // iterations per instance from the last tuning solve
   std::vector<void*> allocs;
   ~admm_mpc_batch() {
     if (!allocs.empty()) {
@@ -610,7 +612,20 @@ admm_status build_items(admm_mpc_batch* b, const Plan& pl) {
     const MpcInst& I = b->h_inst[i];
     return (double)I.T * (2.0 * I.n * (I.n + I.m) + I.n * I.n + 8.0 * (I.n + I.m));
   };
-  if (pl.order == 1) {
+  // expected duration of a solve: measured iterations x the latency of one
+  // iteration, which grows with the padded state size and with the number
+  // of lockstep wavefronts (fitted to single-instance timings)
+  auto duration = [&](int i) {
+    const MpcInst& I = b->h_inst[i];
+    const double Np = I.n < 4 ? 4.0 : (double)I.n;
+    const int G = (I.T + 63) / 64;
+    const double it = std::max<int32_t>(1, std::abs(b->measured[i]));
+    return it * (0.6 + 0.016 * Np * Np + 0.3 * (G - 1));
+  };
+  if (pl.order == 3 && (int)b->measured.size() == b->n_inst) {
+    std::stable_sort(ids.begin(), ids.end(),
+                     [&](int x, int y) { return duration(x) > duration(y); });
+  } else if (pl.order == 1 || pl.order == 3) {
     std::stable_sort(ids.begin(), ids.end(), [&](int x, int y) { return cost(x) > cost(y); });
   } else if (pl.order == 2) {
     std::stable_sort(ids.begin(), ids.end(), [&](int x, int y) {
@@ -833,7 +848,7 @@ admm_status admm_mpc_batch_solve(admm_mpc_batch* b, const float* x0, const float
 admm_status admm_mpc_batch_set_plan(admm_mpc_batch* b, int32_t pack1, int32_t order, int32_t grid) {
   admmi::clear_err();
   if (!b) return admmi::set_err(ADMM_E_ARG, "batch is NULL");
-  if ((pack1 != 1 && pack1 != 2 && pack1 != 4) || order < 0 || order > 2 || grid < 0)
+  if ((pack1 != 1 && pack1 != 2 && pack1 != 4) || order < 0 || order > 3 || grid < 0)
     return admmi::set_err(ADMM_E_ARG, "bad plan");
   ADMM_HIP(hipSetDevice(b->device));
   Plan p;
@@ -862,9 +877,21 @@ admm_status admm_mpc_batch_tune(admm_mpc_batch* b, const float* x0, float tol, i
   if (!b || !x0 || !z_scratch || !iters_scratch) return admmi::set_err(ADMM_E_ARG, "NULL argument");
   ADMM_HIP(hipSetDevice(b->device));
   hipStream_t st = (hipStream_t)stream;
+  // one cold solve first: its iteration counts drive the measured order
+  {
+    admm_status s = build_items(b, Plan());
+    if (s) return s;
+    s = launch_solve(b, x0, nullptr, nullptr, tol, max_iter, z_scratch, iters_scratch, st, nullptr,
+                     nullptr);
+    if (s) return s;
+    b->measured.assign(b->n_inst, 0);
+    ADMM_HIP(hipMemcpyAsync(b->measured.data(), iters_scratch, sizeof(int32_t) * b->n_inst,
+                            hipMemcpyDeviceToHost, st));
+    ADMM_HIP(hipStreamSynchronize(st));
+  }
   std::vector<Plan> cands;
   for (int pack : {4, 2, 1})
-    for (int order : {1, 2})
+    for (int order : {1, 2, 3})
       for (int gmul : {0, 1}) {
         Plan p;
         p.pack1 = pack;

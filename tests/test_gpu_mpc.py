@@ -145,9 +145,14 @@ def test_plans_and_autotuner_do_not_change_results():
     zs = torch.zeros(b.z_total, device="cuda")
     its = torch.zeros(b.n_inst, dtype=torch.int32, device="cuda")
     times = b.tune(x0, zs, its, tol=1e-4, reps=1)
-    assert len(times) >= 6 and all(t > 0 for t in times)
+    assert len(times) == 18 and all(t > 0 for t in times)
     z, it = _solve(b, insts, tol=1e-4, max_iter=10000)
     assert np.array_equal(z, ref_z) and np.array_equal(it, ref_it)
+    # longest measured solve first (the tuning run recorded the iterations)
+    for pack, grid in [(4, 0), (1, 96)]:
+        b.set_plan(pack, 3, grid)
+        z, it = _solve(b, insts, tol=1e-4, max_iter=10000)
+        assert np.array_equal(z, ref_z) and np.array_equal(it, ref_it)
 
 
 def test_max_iter_reported_negative():
