@@ -140,7 +140,7 @@ def bench_warmstart(torch, args):
         X, Z = ws.generate(args.ws_samples, seed=3000 + s)
         gen_s += time.perf_counter() - t0
         t0 = time.perf_counter()
-        hist = ws.train(X, Z, epochs=args.ws_epochs, lr=1e-3, lr_final=1e-4)
+        hist = ws.train(X, Z, epochs=args.ws_epochs, lr=1e-3, lr_final=1e-5)
         train_s += time.perf_counter() - t0
         losses.append(hist[-1])
         del X, Z
@@ -176,7 +176,7 @@ def main():
     ap.add_argument("--no-mpc", action="store_true", help="skip the batched MPC workloads")
     ap.add_argument("--ws-samples", type=int, default=1_000_000,
                     help="ADMM solutions per system for training the warm-start network")
-    ap.add_argument("--ws-epochs", type=int, default=8)
+    ap.add_argument("--ws-epochs", type=int, default=32)
     ap.add_argument("--ws-systems", type=int, default=8)
     args = ap.parse_args()
     if args.gpus != 1:

@@ -498,43 +498,88 @@ __global__ void reset_counter_kernel(int32_t* c) {
 //   rho u[quad u] = -R u_t, rho u[box] = B^T mu_t + R u_t, rho u[quad x] = -Q x_{t+1}
 // One 64-lane workgroup per instance: lanes r < n run the backward pass,
 // then every lane writes the duals of its time steps.
-__global__ __launch_bounds__(64) void mpc_dual_kernel(const MpcInst* inst, const float* par,
-                                                      const float* z, float* u, float inv_rho) {
-  __shared__ float mu[TMAX * MN];
-  const MpcInst I = inst[blockIdx.x];
-  const int T = I.T, n = I.n, m = I.m, k = n + m;
+// Dual completion, four instances per wavefront (one 16-lane DPP row
+// each; lane i of a row is state component i).  Backward over t, with
+// X[t] = x_{t+1} and U[t] = u_t from z:
+//   mu_{T-1} = Q X[T-1],  mu_{t-1} = A^T mu_t + Q X[t-1],
+// and at step t (u layout [dx n | du m | dx1 n | qu m | bx m | qx n]):
+//   dx = -A^T mu_t (0 at t = 0), du = -B^T mu_t, dx1 = mu_t,
+//   qu = -R U[t], bx = B^T mu_t + R U[t], qx = -Q X[t], all divided by rho.
+// Lane i holds column i of A and of B; mu_t[j] reaches every lane of the
+// row by DPP row broadcast (row_newbcast:j), so a step is 2n FMAs.  The
+// instance's z is staged in LDS first.  Rows run max(T) steps; a row
+// whose instance is shorter or absent computes on zeros and stores
+// nothing.
+template <int J>
+__device__ __forceinline__ float row_bcast(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x150 + J, 0xF, 0xF, false));
+}
+
+__global__ __launch_bounds__(64) void mpc_dual_kernel(const MpcInst* inst, int32_t n_inst,
+                                                      const float* par, const float* z, float* u,
+                                                      float inv_rho) {
+  __shared__ float zs[4][TMAX * 16];
+  const int lane = threadIdx.x, row = lane >> 4, li = lane & 15;
+  const int id = blockIdx.x * 4 + row;
+  const bool have = id < n_inst;
+  const MpcInst I = inst[have ? id : 0];
+  const int T = have ? I.T : 0, n = I.n, m = I.m, k = n + m;
   const int N = pad_n(n);
   const ParOff o = par_offsets(N);
   const float* P = par + I.par_off;
   const float* zz = z + I.z_off;
-  const int lane = threadIdx.x;
-  for (int t = T - 1; t >= 0; --t) {
-    if (lane < n) {
-      float v = P[o.q + lane] * zz[(int64_t)t * k + m + lane];
-      if (t + 1 < T)
-        for (int j = 0; j < n; ++j) v += P[o.A + j * N + lane] * mu[(t + 1) * MN + j];
-      mu[t * MN + lane] = v;
-    }
-    __syncthreads();
+  // eight loads in flight per lane before the first store waits
+#pragma unroll 8
+  for (int e = li; e < T * k; e += 16) zs[row][e] = zz[e];
+  float acol[MN], bcol[MN];
+#pragma unroll
+  for (int j = 0; j < MN; ++j) {
+    acol[j] = (li < n && j < n) ? P[o.A + j * N + li] : 0.f;
+    bcol[j] = (li < m && j < n) ? P[o.B + j * MM + li] : 0.f;
   }
-  for (int t = lane; t < T; t += 64) {
-    float* ut = u + I.u_off + (int64_t)t * 3 * k;
-    const float* zt = zz + (int64_t)t * k;
-    const float* mt = mu + t * MN;
-    for (int i = 0; i < n; ++i) {
-      float s = 0.f;
-      for (int r = 0; r < n; ++r) s += P[o.A + r * N + i] * mt[r];
-      ut[i] = (t >= 1) ? -s * inv_rho : 0.f;                  // dyn, x_t edge
-      ut[n + m + i] = mt[i] * inv_rho;                        // dyn, x_{t+1} edge
-      ut[2 * n + 3 * m + i] = -P[o.q + i] * zt[m + i] * inv_rho;  // quad on x_{t+1}
+  const float ql = li < n ? P[o.q + li] : 0.f;
+  const float rl = li < m ? P[o.r + li] : 0.f;
+  __syncthreads();
+  int Tmax = T;
+  Tmax = max(Tmax, __shfl_xor(Tmax, 16, 64));
+  Tmax = max(Tmax, __shfl_xor(Tmax, 32, 64));
+  const float* zr = zs[row];
+  float mu = (T > 0 && li < n) ? ql * zr[(T - 1) * k + m + li] : 0.f;
+  for (int s = 0; s < Tmax; ++s) {
+    const int t = T - 1 - s;            // this row's step (< 0: nothing to do)
+    // this step's x_{t+1} and u_t and the previous step's x_t, read together
+    // (indices clamped into the instance; unused values are never stored)
+    const int tc = t > 0 ? t : 0, tp = t > 1 ? t - 1 : 0;
+    const int ix = m + (li < n ? li : 0), iu = li < m ? li : 0;
+    const float xt = zr[tc * k + ix];
+    const float uu = zr[tc * k + iu];
+    const float xp = zr[tp * k + ix];
+    float a = 0.f, b = 0.f;
+    static_assert(MN == 12, "the broadcast sequence below covers 12 components");
+#define ADMM_DUAL_TERM(J)                   \
+  {                                         \
+    const float mj = row_bcast<J>(mu);      \
+    a = fmaf(acol[J], mj, a);               \
+    b = fmaf(bcol[J], mj, b);               \
+  }
+    ADMM_DUAL_TERM(0) ADMM_DUAL_TERM(1) ADMM_DUAL_TERM(2) ADMM_DUAL_TERM(3)
+    ADMM_DUAL_TERM(4) ADMM_DUAL_TERM(5) ADMM_DUAL_TERM(6) ADMM_DUAL_TERM(7)
+    ADMM_DUAL_TERM(8) ADMM_DUAL_TERM(9) ADMM_DUAL_TERM(10) ADMM_DUAL_TERM(11)
+#undef ADMM_DUAL_TERM
+    if (t >= 0) {
+      float* ut = u + I.u_off + (int64_t)t * 3 * k;
+      if (li < n) {
+        ut[li] = t >= 1 ? -a * inv_rho : 0.f;             // dynamics, x_t edge
+        ut[n + m + li] = mu * inv_rho;                     // dynamics, x_{t+1} edge
+        ut[2 * n + 3 * m + li] = -ql * xt * inv_rho;       // quadratic on x_{t+1}
+      }
+      if (li < m) {
+        ut[n + li] = -b * inv_rho;                         // dynamics, u_t edge
+        ut[2 * n + m + li] = -rl * uu * inv_rho;           // quadratic on u_t
+        ut[2 * n + 2 * m + li] = (b + rl * uu) * inv_rho;  // box on u_t
+      }
     }
-    for (int j = 0; j < m; ++j) {
-      float s = 0.f;
-      for (int r = 0; r < n; ++r) s += P[o.B + r * MM + j] * mt[r];
-      ut[n + j] = -s * inv_rho;                                // dyn, u_t edge
-      ut[2 * n + m + j] = -P[o.r + j] * zt[j] * inv_rho;       // quad on u_t
-      ut[2 * n + 2 * m + j] = (s + P[o.r + j] * zt[j]) * inv_rho;  // box on u_t
-    }
+    mu = (t >= 1 && li < n) ? a + ql * xp : 0.f;
   }
 }
 
@@ -820,7 +865,7 @@ admm_status admm_mpc_batch_dual_complete(admm_mpc_batch* b, const float* z, floa
   admmi::clear_err();
   if (!b || !z || !u) return admmi::set_err(ADMM_E_ARG, "NULL argument");
   ADMM_HIP(hipSetDevice(b->device));
-  mpc_dual_kernel<<<b->n_inst, 64, 0, (hipStream_t)stream>>>(b->d_inst, b->d_par, z, u,
+  mpc_dual_kernel<<<(b->n_inst + 3) / 4, 64, 0, (hipStream_t)stream>>>(b->d_inst, b->n_inst, b->d_par, z, u,
                                                               (float)(1.0 / b->rho));
   ADMM_HIP(hipGetLastError());
   return ADMM_OK;
@@ -838,7 +883,8 @@ admm_status admm_mpc_batch_solve(admm_mpc_batch* b, const float* x0, const float
   hipStream_t st = (hipStream_t)stream;
   const float* uinit = nullptr;
   if (dual_mode == 1) {
-    mpc_dual_kernel<<<b->n_inst, 64, 0, st>>>(b->d_inst, b->d_par, z_init, b->d_u, (float)(1.0 / b->rho));
+    mpc_dual_kernel<<<(b->n_inst + 3) / 4, 64, 0, st>>>(b->d_inst, b->n_inst, b->d_par, z_init, b->d_u,
+                                                          (float)(1.0 / b->rho));
     ADMM_HIP(hipGetLastError());
     uinit = b->d_u;
   }
