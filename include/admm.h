@@ -288,7 +288,8 @@ admm_status admm_mpc_batch_destroy(admm_mpc_batch* b);
 typedef struct admm_mlp admm_mlp;
 
 /* Allocate parameters, Adam moments and activations for batches up to
- * max_batch on `device`; parameters start at zero. */
+ * max_batch on `device`; parameters start at zero.  ADMM_E_UNSUPPORTED when
+ * max_batch times the widest layer reaches 2^31 elements. */
 admm_status admm_mlp_create(int32_t n_in, int32_t hidden, int32_t n_out, int32_t max_batch,
                             int32_t device, admm_mlp** out);
 /* Number of parameters (-1 for NULL). */

@@ -60,17 +60,17 @@ __global__ __launch_bounds__(GT) void gemm_kernel(int M, int N, int K, int kc,
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
-  for (int k0 = kbeg; k0 < kend; k0 += BK) {
-    // A tile 64 x 32 and B tile 32 x 64: 2048 elements each, 8 per thread
+  // The next K tile is read from global memory into registers while the
+  // current one is multiplied from LDS.
+  float ra[8], rb[8];
+  auto load_tile = [&](int k0) {
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       const int e = t + q * GT;
       int r, c;
       if (TA) { c = e / BM; r = e % BM; } else { r = e / BK; c = e % BK; }
       const int gm = m0 + r, gk = k0 + c;
-      float v = 0.f;
-      if (gm < M && gk < kend) v = TA ? A[(int64_t)gk * lda + gm] : A[(int64_t)gm * lda + gk];
-      As[r][c] = f2bf(v);
+      ra[q] = (gm < M && gk < kend) ? (TA ? A[(int64_t)gk * lda + gm] : A[(int64_t)gm * lda + gk]) : 0.f;
     }
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
@@ -78,11 +78,28 @@ __global__ __launch_bounds__(GT) void gemm_kernel(int M, int N, int K, int kc,
       int r, c;
       if (TB) { c = e / BK; r = e % BK; } else { r = e / BN; c = e % BN; }
       const int gk = k0 + r, gn = n0 + c;
-      float v = 0.f;
-      if (gk < kend && gn < N) v = TB ? B[(int64_t)gn * ldb + gk] : B[(int64_t)gk * ldb + gn];
-      Bs[r][c] = f2bf(v);
+      rb[q] = (gk < kend && gn < N) ? (TB ? B[(int64_t)gn * ldb + gk] : B[(int64_t)gk * ldb + gn]) : 0.f;
+    }
+  };
+  if (kbeg < kend) load_tile(kbeg);
+  for (int k0 = kbeg; k0 < kend; k0 += BK) {
+    // A tile 64 x 32 and B tile 32 x 64: 2048 elements each, 8 per thread
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int e = t + q * GT;
+      int r, c;
+      if (TA) { c = e / BM; r = e % BM; } else { r = e / BK; c = e % BK; }
+      As[r][c] = f2bf(ra[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int e = t + q * GT;
+      int r, c;
+      if (TB) { c = e / BK; r = e % BK; } else { r = e / BN; c = e % BN; }
+      Bs[r][c] = f2bf(rb[q]);
     }
     __syncthreads();
+    if (k0 + BK < kend) load_tile(k0 + BK);
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 16) {
       const int kq = kk + (lane >> 4) * 4;
@@ -137,6 +154,19 @@ __global__ void splitk_sum_kernel(int64_t n, int nz, const float* __restrict__ w
   out[i] = s;
 }
 
+// The same reduction of a [M][N] product followed by the ReLU-mask
+// epilogue: out[r][c] = mask[r][c] > 0 ? sum : 0.
+__global__ void splitk_sum_mask_kernel(int64_t n, int N, int nz, const float* __restrict__ ws,
+                                       const float* __restrict__ mask, int ldm,
+                                       float* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float s = 0.f;
+  for (int z = 0; z < nz; ++z) s += ws[(int64_t)z * n + i];
+  const int64_t r = i / N, c = i % N;
+  out[i] = mask[r * ldm + c] > 0.f ? s : 0.f;
+}
+
 // Loss on normalised outputs: with yh the network's raw output and
 // th = (target - mu) / sd per column, dY = 2 (yh - th) / (rows * cols);
 // per-block partial sums of (yh - th)^2.
@@ -146,8 +176,10 @@ __global__ __launch_bounds__(256) void mse_grad_kernel(int64_t n, int cols, cons
                                                        float* part) {
   __shared__ float red[256];
   float s = 0.f;
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
-    const int c = (int)(i % cols);
+  // n < 2^31 (checked on the host): 32-bit index arithmetic
+  const int nn = (int)n;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < nn; i += gridDim.x * 256) {
+    const int c = i % cols;
     const float d = y[i] - (tg[i] - mu[c]) / sd[c];
     dy[i] = 2.f * d * scale;
     s += d * d;
@@ -161,11 +193,18 @@ __global__ __launch_bounds__(256) void mse_grad_kernel(int64_t n, int cols, cons
   if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
 
+// Sum of the per-block partials in a fixed order: 64 lanes sum strided
+// subsets in order, then lane 0 adds the 64 results in lane order.
 __global__ void finish_loss_kernel(int nb, const float* part, float scale, float* loss) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    float s = 0.f;
-    for (int i = 0; i < nb; ++i) s += part[i];
-    *loss = s * scale;
+  __shared__ float r64[64];
+  float s = 0.f;
+  for (int i = threadIdx.x; i < nb; i += 64) s += part[i];
+  r64[threadIdx.x] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float t = 0.f;
+    for (int i = 0; i < 64; ++i) t += r64[i];
+    *loss = t * scale;
   }
 }
 
@@ -215,7 +254,7 @@ __global__ void fill_kernel(int n, float v, float* a) {
 // Bias gradients db[c] = sum_r dY[r][c] in two deterministic stages:
 // colsum_part sums chunks of CS_ROWS rows in order into ws[k][c], and
 // splitk_sum_kernel adds the chunks in order.
-constexpr int CS_ROWS = 32;
+constexpr int CS_ROWS = 128;
 __global__ void colsum_part_kernel(int rows, int cols, const float* __restrict__ dY,
                                    float* __restrict__ ws) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
@@ -223,6 +262,7 @@ __global__ void colsum_part_kernel(int rows, int cols, const float* __restrict__
   const int r0 = blockIdx.y * CS_ROWS;
   const int r1 = r0 + CS_ROWS < rows ? r0 + CS_ROWS : rows;
   float s = 0.f;
+#pragma unroll 8
   for (int r = r0; r < r1; ++r) s += dY[(int64_t)r * cols + c];
   ws[(int64_t)blockIdx.y * cols + c] = s;
 }
@@ -252,6 +292,7 @@ struct admm_mlp {
   float* part = nullptr;
   float *mu = nullptr, *sd = nullptr;  // fixed output affine y = mu + sd * yhat
   float* ws = nullptr;                 // split-K partial products
+  int64_t ws_n = 0;                    // its size in floats
   float* cs = nullptr;                 // bias-gradient chunk sums
   int64_t step = 0;
   std::vector<void*> allocs;
@@ -265,7 +306,7 @@ struct admm_mlp {
 
 namespace {
 
-constexpr int LOSS_BLOCKS = 256;
+constexpr int LOSS_BLOCKS = 1024;
 
 admm_status mlp_alloc(admm_mlp* n, float** q, int64_t count) {
   ADMM_HIP(hipMalloc((void**)q, (size_t)std::max<int64_t>(count, 1) * sizeof(float)));
@@ -278,22 +319,31 @@ constexpr int MAX_SPLITS = 32;
 template <bool TA, bool TB, int EPI>
 void gemm(int M, int N, int K, const float* A, int lda, const float* B, int ldb, float* C, int ldc,
           const float* bias, const float* mask, int ldm, hipStream_t st,
-          const float* mu = nullptr, const float* sd = nullptr, float* ws = nullptr) {
+          const float* mu = nullptr, const float* sd = nullptr, float* ws = nullptr,
+          int64_t ws_n = 0) {
   const int gm = (M + BM - 1) / BM, gn = (N + BN - 1) / BN;
   int splits = 1;
-  if (EPI == EPI_PLAIN && ws != nullptr && ldc == N) {
+  if ((EPI == EPI_PLAIN || EPI == EPI_MASK) && ws != nullptr && ldc == N) {
     // enough workgroups to fill the device, at least 128 of K per split
     splits = std::max(1, std::min(MAX_SPLITS, std::min((1024 + gm * gn - 1) / (gm * gn), K / 128)));
+    splits = (int)std::max<int64_t>(1, std::min<int64_t>(splits, ws_n / ((int64_t)M * N)));
   }
   const int kc = ((K + splits - 1) / splits + BK - 1) / BK * BK;
   splits = (K + kc - 1) / kc;
   dim3 grid(gn, gm, splits);
-  float* dst = splits > 1 ? ws : C;
-  gemm_kernel<TA, TB, EPI><<<grid, GT, 0, st>>>(M, N, K, kc, A, lda, B, ldb, dst, ldc, bias, mask,
-                                                 ldm, mu, sd);
   if (splits > 1) {
+    // plain partial products; the reduction applies the mask
+    gemm_kernel<TA, TB, EPI_PLAIN><<<grid, GT, 0, st>>>(M, N, K, kc, A, lda, B, ldb, ws, ldc,
+                                                         nullptr, nullptr, 0, nullptr, nullptr);
     const int64_t n = (int64_t)M * N;
-    splitk_sum_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(n, splits, ws, C);
+    if (EPI == EPI_MASK)
+      splitk_sum_mask_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(n, N, splits, ws, mask,
+                                                                          ldm, C);
+    else
+      splitk_sum_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(n, splits, ws, C);
+  } else {
+    gemm_kernel<TA, TB, EPI><<<grid, GT, 0, st>>>(M, N, K, kc, A, lda, B, ldb, C, ldc, bias, mask,
+                                                   ldm, mu, sd);
   }
 }
 
@@ -330,19 +380,19 @@ void backward(admm_mlp* n, const float* x, const float* tg, int batch, float* lo
   float* g = n->g;
   // layer 3
   gemm<true, false, EPI_PLAIN>(n->n_out, n->hid, batch, n->dy, n->n_out, n->h2, n->hid, g + n->oW3,
-                               n->hid, nullptr, nullptr, 0, st, nullptr, nullptr, n->ws);
+                               n->hid, nullptr, nullptr, 0, st, nullptr, nullptr, n->ws, n->ws_n);
   colsum(batch, n->n_out, n->dy, g + n->ob3, n->cs, st);
   gemm<false, false, EPI_MASK>(batch, n->hid, n->n_out, n->dy, n->n_out, n->p + n->oW3, n->hid,
-                               n->dh2, n->hid, nullptr, n->h2, n->hid, st);
+                               n->dh2, n->hid, nullptr, n->h2, n->hid, st, nullptr, nullptr, n->ws, n->ws_n);
   // layer 2
   gemm<true, false, EPI_PLAIN>(n->hid, n->hid, batch, n->dh2, n->hid, n->h1, n->hid, g + n->oW2,
-                               n->hid, nullptr, nullptr, 0, st, nullptr, nullptr, n->ws);
+                               n->hid, nullptr, nullptr, 0, st, nullptr, nullptr, n->ws, n->ws_n);
   colsum(batch, n->hid, n->dh2, g + n->ob2, n->cs, st);
   gemm<false, false, EPI_MASK>(batch, n->hid, n->hid, n->dh2, n->hid, n->p + n->oW2, n->hid,
-                               n->dh1, n->hid, nullptr, n->h1, n->hid, st);
+                               n->dh1, n->hid, nullptr, n->h1, n->hid, st, nullptr, nullptr, n->ws, n->ws_n);
   // layer 1
   gemm<true, false, EPI_PLAIN>(n->hid, n->n_in, batch, n->dh1, n->hid, x, n->n_in, g + n->oW1,
-                               n->n_in, nullptr, nullptr, 0, st, nullptr, nullptr, n->ws);
+                               n->n_in, nullptr, nullptr, 0, st, nullptr, nullptr, n->ws, n->ws_n);
   colsum(batch, n->hid, n->dh1, g + n->ob1, n->cs, st);
 }
 
@@ -357,6 +407,8 @@ admm_status admm_mlp_create(int32_t n_in, int32_t hidden, int32_t n_out, int32_t
   *out = nullptr;
   if (n_in < 1 || hidden < 1 || n_out < 1 || max_batch < 1)
     return admmi::set_err(ADMM_E_ARG, "sizes must be >= 1");
+  if ((int64_t)max_batch * std::max(std::max(n_in, hidden), n_out) >= (1LL << 31))
+    return admmi::set_err(ADMM_E_UNSUPPORTED, "max_batch x layer width must stay below 2^31");
   std::unique_ptr<admm_mlp> n(new admm_mlp());
   n->device = device;
   n->n_in = n_in;
@@ -389,7 +441,8 @@ admm_status admm_mlp_create(int32_t n_in, int32_t hidden, int32_t n_out, int32_t
   {
     const int64_t big = std::max<int64_t>((int64_t)n_out * hidden,
                                           std::max<int64_t>((int64_t)hidden * hidden, (int64_t)hidden * n_in));
-    if ((s = mlp_alloc(n.get(), &n->ws, big * MAX_SPLITS))) return s;
+    n->ws_n = std::max<int64_t>(big, (int64_t)max_batch * hidden) * MAX_SPLITS / 4;
+    if ((s = mlp_alloc(n.get(), &n->ws, n->ws_n))) return s;
     const int64_t chunks = (max_batch + CS_ROWS - 1) / CS_ROWS;
     if ((s = mlp_alloc(n.get(), &n->cs, chunks * std::max(n_out, hidden)))) return s;
   }
