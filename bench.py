@@ -180,7 +180,7 @@ def main():
     ap.add_argument("--ws-systems", type=int, default=8)
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not "
+        print(f"bench.py runs on one GPU; --gpus {args.gpus} is not "
               "supported (the multi-GPU sharding is a design note only).", file=sys.stderr)
         sys.exit(2)
 

@@ -45,7 +45,7 @@ typedef enum {
   ADMM_E_HIP = 4,          /* a HIP runtime call failed */
   ADMM_E_OOM = 5,          /* device allocation failed */
   ADMM_E_NO_DEVICE = 6,    /* no usable GPU (validation still ran) */
-  ADMM_E_UNSUPPORTED = 7   /* valid request outside this build's limits */
+  ADMM_E_UNSUPPORTED = 7   /* valid request outside the library's limits */
 } admm_status;
 
 /* Factor kinds (the proximal operators of the paper's appendix).
