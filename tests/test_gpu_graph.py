@@ -403,3 +403,10 @@ def test_pair_tiles_with_entity_table(pair_state):
     assert g.info()["n_pair_tiles"] > 0
     _one_step(p, 30, FP32, 1e-5, steps=3, driver=A.DRIVER_LAUNCHES, pair_state=pair_state)
     _traj(p, 12, FP64, 1e-9, driver=A.DRIVER_LAUNCHES)
+
+
+@pytest.mark.parametrize("pair_state", [A.PAIR_STATE_AUTO, A.PAIR_STATE_DENSE])
+def test_full_size_packing_5000_steps(pair_state):
+    """5000 disks (3160 tiles, state beyond the Infinity Cache): three steps
+    from a common state against the oracle, both pair states."""
+    _one_step(W.workload("packing_sq5000"), 10, FP32, 1e-5, steps=3, pair_state=pair_state)
