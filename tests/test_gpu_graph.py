@@ -410,3 +410,32 @@ def test_full_size_packing_5000_steps(pair_state):
     """5000 disks (3160 tiles, state beyond the Infinity Cache): three steps
     from a common state against the oracle, both pair states."""
     _one_step(W.workload("packing_sq5000"), 10, FP32, 1e-5, steps=3, pair_state=pair_state)
+
+
+def _multiplicity_graph(counts, seed):
+    """Scalar variables, variable i carrying counts[i] quadratic factors
+    (weights U[0.1, 2]): z-lists of every class and stride layout (long
+    lists, medium lists of mixed length, short lists, an empty list)."""
+    rng = np.random.default_rng(seed)
+    ids = np.repeat(np.arange(len(counts), dtype=np.int32), counts)
+    groups = [W.FactorGroup("quad", ids[:, None], rng.uniform(0.1, 2.0, (ids.size, 1)))]
+    z0 = rng.standard_normal(len(counts))
+    return W.Problem("multiplicity", np.ones(len(counts), np.int32), groups, z0)
+
+
+@pytest.mark.parametrize("driver", [A.DRIVER_LAUNCHES, A.DRIVER_RESIDENT])
+def test_zlist_classes_and_layouts(driver):
+    # one list of 200 (one workgroup), one of 100 and 1000 of 5 (medium lists
+    # too uneven to pad: explicit ranges), 40 of 3 (short), one of 0
+    counts = np.r_[200, 100, np.full(1000, 5), np.full(40, 3), 0]
+    p = _multiplicity_graph(counts, seed=17)
+    if driver == A.DRIVER_RESIDENT:     # small enough for the LDS image in FP64
+        p = _multiplicity_graph(np.r_[150, 60, np.full(150, 5), np.full(20, 3), 0], seed=18)
+    g, o = _traj(p, 30, FP64, 1e-9, driver=driver)
+    assert g.info()["driver"] == driver
+    assert g.z()[-1] == p.z0[-1]
+    _traj(p, 30, FP32, 1e-4, driver=driver)
+    # medium lists of equal length: padded stride layout
+    nq = 500 if driver == A.DRIVER_LAUNCHES else 100
+    q = _multiplicity_graph(np.r_[np.full(nq, 7), np.full(10, 2)], seed=19)
+    _traj(q, 30, FP64, 1e-9, driver=driver)
