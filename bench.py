@@ -36,9 +36,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+WORKLOAD_DESC = {
+    "packing_sq2000": dict(n_circles=2000, container="unit square", seed=1001),
+    "packing_sq5000": dict(n_circles=5000, container="unit square", seed=1005),
+    "svm_100k_d20": dict(points=100000, d=20, seed=1002),
+}
 KERNEL_SOURCES = ["paper_1603_02526_amd/csrc/graph_kernels.h",
                   "paper_1603_02526_amd/csrc/internal.h"]
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "xpass_packing_sq2000_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "xpass_traffic.json")
 
 
 def kernel_sha() -> str:
@@ -49,17 +54,21 @@ def kernel_sha() -> str:
     return h.hexdigest()[:16]
 
 
-def committed_traffic():
-    """HBM bytes per x-pass launch from the committed counter summary, or
-    None when it is missing or was taken on a different kernel source."""
+def committed_traffic(workload: str, pair_state: str):
+    """HBM bytes per x-pass launch from the committed counter summaries for
+    this workload and pair state, or None when missing or taken on a
+    different kernel source."""
     try:
         with open(TRAFFIC_FILE) as f:
-            t = json.load(f)
+            entries = json.load(f)
     except (OSError, ValueError):
         return None
-    if t.get("kernel_sha") != kernel_sha():
-        return None
-    return t.get("traffic_bytes_per_launch")
+    sha = kernel_sha()
+    for t in entries:
+        if (t.get("workload") == workload and t.get("pair_state") == pair_state
+                and t.get("kernel_sha") == sha):
+            return t.get("traffic_bytes_per_launch")
+    return None
 
 
 def time_solve(g, iters, steps, warmup, torch, stream):
@@ -178,6 +187,11 @@ def main():
                     help="ADMM solutions per system for training the warm-start network")
     ap.add_argument("--ws-epochs", type=int, default=32)
     ap.add_argument("--ws-systems", type=int, default=8)
+    ap.add_argument("--workload", default="packing_sq2000",
+                    choices=["packing_sq2000", "packing_sq5000", "svm_100k_d20"],
+                    help="graph of the headline line (default: the 2000-disk packing)")
+    ap.add_argument("--pair-state", default="auto", choices=["auto", "dense"],
+                    help="pair-tile state of the headline graph")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not "
@@ -192,9 +206,11 @@ def main():
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
 
-    name = "packing_sq2000"
+    name = args.workload
     prob = W.workload(name)
-    g = A.Graph.from_problem(prob, precision=A.FP32, device=0)
+    g = A.Graph.from_problem(prob, precision=A.FP32, device=0,
+                             pair_state=A.PAIR_STATE_DENSE if args.pair_state == "dense"
+                             else A.PAIR_STATE_AUTO)
     info = g.info()
     sec = time_solve(g, args.iters, args.steps, args.warmup, torch, stream)
     value = prob.n_edges * args.iters / sec
@@ -205,11 +221,12 @@ def main():
     x_avg_s = xms * 1e-3 / args.iters
     z_avg_s = zms * 1e-3 / args.iters
     achieved = info["algo_bytes_per_iter"] / x_avg_s / 1e9
-    traffic = committed_traffic()
+    state = "sparse" if info["sparse_pair_state"] else "dense"
+    traffic = committed_traffic(name, state)
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS,
                     unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4),
                     traffic=traffic, kernel="xpass_kernel",
-                    pair_state="sparse" if info["sparse_pair_state"] else "dense",
+                    pair_state=state,
                     algo_bytes_per_launch=info["algo_bytes_per_iter"],
                     avg_launch_us=round(x_avg_s * 1e6, 3),
                     zpass_avg_us=round(z_avg_s * 1e6, 3))
@@ -221,10 +238,10 @@ def main():
                n_gpus=1, steps=args.steps, warmup=args.warmup,
                ms_per_step=sec * 1e3, higher_is_better=True, scaling="weak",
                vs_baseline=None, dtype="f32", data="synthetic",
-               config=dict(workload=name, n_circles=2000, container="unit square",
+               config=dict(workload=name, **WORKLOAD_DESC[name],
                            iterations_per_step=args.iters, edges=prob.n_edges,
                            slots=prob.n_slots, factors=prob.n_factors,
-                           rho=1.0, alpha=1.0, seed=1001),
+                           rho=1.0, alpha=1.0),
                roofline=roofline)
 
     if args.calibrate_copy:
