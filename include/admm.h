@@ -247,6 +247,36 @@ admm_status admm_mpc_batch_solve(admm_mpc_batch* b, const float* x0, const float
 admm_status admm_mpc_batch_dual_complete(admm_mpc_batch* b, const float* z, float* u,
                                          void* stream);
 
+/* Solve from a full ADMM state: z_init [z_total] (NULL: cold start, z = 0)
+ * and per-edge duals u_init [u_total] (NULL: u^0 = 0; needs z_init).  On
+ * exit z_out holds z and, when u_out is not NULL, u_out [u_total] the duals
+ * u = m - z of the last iteration, so a later call can continue the same
+ * iteration from (z_out, u_out) (Algorithm 2 keeps nothing else per edge
+ * when alpha = 1).  Stopping rule and iters_out as in admm_mpc_batch_solve.
+ * Device arrays; z_out must not be z_init and u_out must not be u_init
+ * (ADMM_E_ARG).  Asynchronous on `stream`. */
+admm_status admm_mpc_batch_solve_state(admm_mpc_batch* b, const float* x0, const float* z_init,
+                                       const float* u_init, float tol, int32_t max_iter,
+                                       float* z_out, float* u_out, int32_t* iters_out,
+                                       void* stream);
+
+/* One receding-horizon step for every instance (paper Sec. V-B: in each
+ * controller cycle only the current state changes and the ADMM continues
+ * from the previous cycle's solution).  Device arrays:
+ *   x0_next = A x0 + B u_0 + w, with u_0 the first input of z (w [x0_total]
+ *             may be NULL: no disturbance);
+ *   z_next (may be NULL): z moved one step forward, z'(t) = z(t+1) for
+ *             t < T-1, and the last step u = 0, x = A x_T;
+ *   u_next (given with u, else both NULL): every edge's dual moved with its
+ *             step; the step-1 dual on the dynamics factor's x_1 edge is
+ *             dropped (step 0 has no such edge) and the last step's duals
+ *             are zero, so the duals around each variable keep their sum.
+ * Outputs must not be the corresponding inputs (ADMM_E_ARG).  Asynchronous
+ * on `stream`. */
+admm_status admm_mpc_batch_shift(admm_mpc_batch* b, const float* x0, const float* z,
+                                 const float* u, const float* w, float* x0_next, float* z_next,
+                                 float* u_next, void* stream);
+
 /* Schedule of the persistent launch: pack1 = instances per workgroup for
  * T <= 64 (1, 2 or 4), order (0 as given, 1 most work per iteration first,
  * 2 grouped by (n, m), 3 longest expected solve first: the iteration counts

@@ -14,6 +14,9 @@ the dynamics multipliers mu_t:
     rho u[box u_t]  = B^T mu_t + R u_t
 The returned vector follows the edge order of ``workloads.mpc_graph``.
 
+Receding-horizon shift (``receding_shift``): one controller cycle's update of
+the initial state and of the previous cycle's ADMM state.
+
 Also a plain FP64 MLP (forward, mean-squared-error backward, Adam step) that
 the GPU training kernels are checked against.
 """
@@ -51,6 +54,76 @@ def dual_completion(inst, z, rho: float = 1.0) -> np.ndarray:
         for t in range(T):
             out.append((B.T @ mu[t] + R @ U[t]) / rho)
     return np.concatenate(out)
+
+
+def _edge_blocks(inst):
+    """(start, length) of every dual block of ``workloads.mpc_graph``'s edge
+    order, by name: dyn0 = (u_0, x_1); dyn[t] = (x_t, u_t, x_{t+1}) for
+    t = 1..T-1; qx[t] on x_{t+1}; qu[t] and box[t] on u_t."""
+    T, n, m = inst.T, inst.n, inst.m
+    off = 0
+    blocks = {"dyn0": (off, m + n)}
+    off += m + n
+    for t in range(1, T):
+        blocks[("dyn", t)] = (off, 2 * n + m)
+        off += 2 * n + m
+    for t in range(T):
+        blocks[("qx", t)] = (off, n)
+        off += n
+    for t in range(T):
+        blocks[("qu", t)] = (off, m)
+        off += m
+    if inst.u_box > 0:
+        for t in range(T):
+            blocks[("box", t)] = (off, m)
+            off += m
+    return blocks, off
+
+
+def receding_shift(inst, x0, z, u=None, w=None):
+    """One controller cycle of receding-horizon MPC (Sec. V-B: the state is
+    updated and the ADMM continues from the previous cycle's solution).
+
+    The plant applies the first planned input, x0' = A x0 + B u_0 (+ w).
+    The trajectory moves one step forward: step t of the new z is step t+1
+    of the old one, and the new last step is u = 0, x = A x_T (the old
+    horizon's end propagated with no input).  Every edge's dual moves with
+    its step; the step-1 dynamics factor's dual on x_1 has no counterpart
+    (the step-0 factor has x_0 as a parameter) and is dropped, and the new
+    last step's duals are zero.  ``u`` follows ``workloads.mpc_graph``'s edge
+    order.  Returns (x0', z', u') in FP64 (u' is None when u is)."""
+    T, n, m = inst.T, inst.n, inst.m
+    A, B = np.asarray(inst.A, np.float64), np.asarray(inst.B, np.float64)
+    blk = np.asarray(z, dtype=np.float64).reshape(T, n + m)
+    x0n = A @ np.asarray(x0, np.float64) + B @ blk[0, :m]
+    if w is not None:
+        x0n = x0n + np.asarray(w, np.float64)
+    zn = np.zeros_like(blk)
+    zn[:T - 1] = blk[1:]
+    zn[T - 1, m:] = A @ blk[T - 1, m:]
+    if u is None:
+        return x0n, zn.ravel(), None
+    u = np.asarray(u, dtype=np.float64)
+    blocks, total = _edge_blocks(inst)
+    assert u.shape == (total,)
+    un = np.zeros(total)
+
+    def get(key):
+        s, ln = blocks[key]
+        return u[s:s + ln]
+
+    def put(key, v):
+        s, ln = blocks[key]
+        un[s:s + ln] = v
+
+    if T > 1:
+        put("dyn0", get(("dyn", 1))[n:])        # (u_1, x_2) parts become (u_0, x_1)
+    for t in range(1, T - 1):
+        put(("dyn", t), get(("dyn", t + 1)))
+    for name in ("qx", "qu") + (("box",) if inst.u_box > 0 else ()):
+        for t in range(T - 1):
+            put((name, t), get((name, t + 1)))
+    return x0n, zn.ravel(), un
 
 
 # ---------------------------------------------------------------------------

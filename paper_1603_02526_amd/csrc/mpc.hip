@@ -81,6 +81,7 @@ struct SolveArgs {
   const float* zinit;   // nullable: z0 = 0
   const float* uinit;   // nullable: u0 = 0
   float* zout;
+  float* uout;          // nullable: final per-edge duals
   int32_t* iters;
   const int32_t* items; // [n_items][5]: G, id0..id3 (-1 = none)
   int32_t n_items;
@@ -425,6 +426,27 @@ __device__ __forceinline__ void solve_one(const SolveArgs a, int id, int t, int 
     for (int j = 0; j < MM; ++j) if (j < m) zo[j] = zu[j];
 #pragma unroll
     for (int i = 0; i < N; ++i) if (i < n) zo[m + i] = zx1[i];
+    if (a.uout) {
+      // u = m - z with the final z (the state the next solve continues from);
+      // zxpc already holds the final z of x_t
+      float* uo = a.uout + I.u_off + (int64_t)t * 3 * k;
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        if (i < n) {
+          uo[i] = t >= 1 ? mdx[i] - zxpc[i] : 0.f;
+          uo[n + m + i] = mdx1[i] - zx1[i];
+          uo[2 * n + 3 * m + i] = mqx[i] - zx1[i];
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < MM; ++j) {
+        if (j < m) {
+          uo[n + j] = mdu[j] - zu[j];
+          uo[2 * n + m + j] = mqu[j] - zu[j];
+          uo[2 * n + 2 * m + j] = mbx[j] - zu[j];
+        }
+      }
+    }
   }
   if (t == 0) a.iters[id] = done_it > 0 ? done_it : -a.max_iter;
 }
@@ -449,8 +471,8 @@ __device__ __forceinline__ void solve_dispatch(const SolveArgs a, int id, int t,
 __global__ __launch_bounds__(WGT) void mpc_solve_kernel(
     const MpcInst* __restrict__ inst, const float* __restrict__ par, const float* __restrict__ x0,
     const float* __restrict__ zinit, const float* __restrict__ uinit, float* __restrict__ zout,
-    int32_t* __restrict__ iters, const int32_t* __restrict__ items, int32_t n_items,
-    int32_t* __restrict__ counter, float tol, int32_t max_iter, float rho) {
+    float* __restrict__ uout, int32_t* __restrict__ iters, const int32_t* __restrict__ items,
+    int32_t n_items, int32_t* __restrict__ counter, float tol, int32_t max_iter, float rho) {
   SolveArgs a;
   a.inst = inst;
   a.par = par;
@@ -458,6 +480,7 @@ __global__ __launch_bounds__(WGT) void mpc_solve_kernel(
   a.zinit = zinit;
   a.uinit = uinit;
   a.zout = zout;
+  a.uout = uout;
   a.iters = iters;
   a.items = items;
   a.n_items = n_items;
@@ -580,6 +603,64 @@ __global__ __launch_bounds__(64) void mpc_dual_kernel(const MpcInst* inst, int32
       }
     }
     mu = (t >= 1 && li < n) ? a + ql * xp : 0.f;
+  }
+}
+
+// One receding-horizon step of every instance (the paper's Sec. V-B: each
+// controller cycle updates the current state and continues the ADMM from the
+// previous cycle's solution).  The plant applies the first planned input:
+//   x0' = A x0 + B u_0 (+ w),  u_0 = z of u_0.
+// With zn: the trajectory moves one step forward, z'(t) = z(t+1) for
+// t < T-1, and the new last step holds u = 0 and x = A x_T.  With un: every
+// edge's dual moves with its step (the dynamics factor of step 0 has no x_t
+// edge, so that part of step 1 is dropped) and the new last step's duals are
+// zero; the duals around every variable keep their sum.
+// One workgroup per instance, one thread per step (T <= 256).
+__global__ __launch_bounds__(WGT) void mpc_shift_kernel(
+    const MpcInst* __restrict__ inst, const float* __restrict__ par, const float* __restrict__ x0,
+    const float* __restrict__ z, const float* __restrict__ u, const float* __restrict__ w,
+    float* __restrict__ x0n, float* __restrict__ zn, float* __restrict__ un) {
+  const MpcInst I = inst[blockIdx.x];
+  const int t = threadIdx.x;
+  const int T = I.T, n = I.n, m = I.m, k = n + m;
+  const int Np = pad_n(n);
+  const ParOff o = par_offsets(Np);
+  const float* P = par + I.par_off;
+  const float* zi = z + I.z_off;
+  if (t == 0) {
+    const float* xi = x0 + I.x0_off;
+    for (int r = 0; r < n; ++r) {
+      float s = 0.f;
+      for (int j = 0; j < n; ++j) s = fmaf(P[o.A + r * Np + j], xi[j], s);
+      for (int j = 0; j < m; ++j) s = fmaf(P[o.B + r * MM + j], zi[j], s);
+      if (w) s += w[I.x0_off + r];
+      x0n[I.x0_off + r] = s;
+    }
+  }
+  if (t >= T) return;
+  if (zn) {
+    float* zo = zn + I.z_off + (int64_t)t * k;
+    if (t + 1 < T) {
+      const float* src = zi + (int64_t)(t + 1) * k;
+      for (int q = 0; q < k; ++q) zo[q] = src[q];
+    } else {
+      const float* xT = zi + (int64_t)t * k + m;
+      for (int j = 0; j < m; ++j) zo[j] = 0.f;
+      for (int r = 0; r < n; ++r) {
+        float s = 0.f;
+        for (int j = 0; j < n; ++j) s = fmaf(P[o.A + r * Np + j], xT[j], s);
+        zo[m + r] = s;
+      }
+    }
+  }
+  if (un) {
+    float* uo = un + I.u_off + (int64_t)t * 3 * k;
+    if (t + 1 < T) {
+      const float* src = u + I.u_off + (int64_t)(t + 1) * 3 * k;
+      for (int q = 0; q < 3 * k; ++q) uo[q] = (t == 0 && q < n) ? 0.f : src[q];
+    } else {
+      for (int q = 0; q < 3 * k; ++q) uo[q] = 0.f;
+    }
   }
 }
 
@@ -709,8 +790,8 @@ admm_status build_items(admm_mpc_batch* b, const Plan& pl) {
 }
 
 admm_status launch_solve(admm_mpc_batch* b, const float* x0, const float* zinit, const float* uinit,
-                         float tol, int32_t max_iter, float* zout, int32_t* iters, hipStream_t st,
-                         hipEvent_t e0, hipEvent_t e1) {
+                         float tol, int32_t max_iter, float* zout, float* uout, int32_t* iters,
+                         hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
   reset_counter_kernel<<<1, 64, 0, st>>>(b->d_counter);
   SolveArgs a;
   a.inst = b->d_inst;
@@ -719,6 +800,7 @@ admm_status launch_solve(admm_mpc_batch* b, const float* x0, const float* zinit,
   a.zinit = zinit;
   a.uinit = uinit;
   a.zout = zout;
+  a.uout = uout;
   a.iters = iters;
   a.items = b->d_items;
   a.n_items = b->n_items;
@@ -729,8 +811,8 @@ admm_status launch_solve(admm_mpc_batch* b, const float* x0, const float* zinit,
   int grid = b->plan.grid > 0 ? b->plan.grid : b->resident;
   grid = std::max(1, std::min(grid, b->n_items));
   hipExtLaunchKernelGGL(mpc_solve_kernel, dim3(grid), dim3(WGT), 0, st, e0, e1, 0,
-                        (const MpcInst*)a.inst, a.par, a.x0, a.zinit, a.uinit, a.zout, a.iters,
-                        a.items, a.n_items, a.counter, a.tol, a.max_iter, a.rho);
+                        (const MpcInst*)a.inst, a.par, a.x0, a.zinit, a.uinit, a.zout, a.uout,
+                        a.iters, a.items, a.n_items, a.counter, a.tol, a.max_iter, a.rho);
   ADMM_HIP(hipGetLastError());
   return ADMM_OK;
 }
@@ -888,7 +970,38 @@ admm_status admm_mpc_batch_solve(admm_mpc_batch* b, const float* x0, const float
     ADMM_HIP(hipGetLastError());
     uinit = b->d_u;
   }
-  return launch_solve(b, x0, z_init, uinit, tol, max_iter, z_out, iters_out, st, nullptr, nullptr);
+  return launch_solve(b, x0, z_init, uinit, tol, max_iter, z_out, nullptr, iters_out, st, nullptr,
+                      nullptr);
+}
+
+admm_status admm_mpc_batch_solve_state(admm_mpc_batch* b, const float* x0, const float* z_init,
+                                       const float* u_init, float tol, int32_t max_iter,
+                                       float* z_out, float* u_out, int32_t* iters_out,
+                                       void* stream) {
+  admmi::clear_err();
+  if (!b || !x0 || !z_out || !iters_out) return admmi::set_err(ADMM_E_ARG, "NULL argument");
+  if (max_iter < 1 || !(tol > 0.f)) return admmi::set_err(ADMM_E_ARG, "need max_iter >= 1 and tol > 0");
+  if (u_init && !z_init) return admmi::set_err(ADMM_E_ARG, "u_init needs z_init");
+  if (u_out && (u_out == u_init)) return admmi::set_err(ADMM_E_ARG, "u_out must not be u_init");
+  if (z_out == z_init) return admmi::set_err(ADMM_E_ARG, "z_out must not be z_init");
+  ADMM_HIP(hipSetDevice(b->device));
+  return launch_solve(b, x0, z_init, u_init, tol, max_iter, z_out, u_out, iters_out,
+                      (hipStream_t)stream, nullptr, nullptr);
+}
+
+admm_status admm_mpc_batch_shift(admm_mpc_batch* b, const float* x0, const float* z, const float* u,
+                                 const float* w, float* x0_next, float* z_next, float* u_next,
+                                 void* stream) {
+  admmi::clear_err();
+  if (!b || !x0 || !z || !x0_next) return admmi::set_err(ADMM_E_ARG, "NULL argument");
+  if ((u == nullptr) != (u_next == nullptr)) return admmi::set_err(ADMM_E_ARG, "u and u_next go together");
+  if (x0_next == x0 || (z_next && z_next == z) || (u_next && u_next == u))
+    return admmi::set_err(ADMM_E_ARG, "outputs must not overlap the inputs");
+  ADMM_HIP(hipSetDevice(b->device));
+  mpc_shift_kernel<<<b->n_inst, WGT, 0, (hipStream_t)stream>>>(b->d_inst, b->d_par, x0, z, u, w,
+                                                              x0_next, z_next, u_next);
+  ADMM_HIP(hipGetLastError());
+  return ADMM_OK;
 }
 
 admm_status admm_mpc_batch_set_plan(admm_mpc_batch* b, int32_t pack1, int32_t order, int32_t grid) {
@@ -927,8 +1040,8 @@ admm_status admm_mpc_batch_tune(admm_mpc_batch* b, const float* x0, float tol, i
   {
     admm_status s = build_items(b, Plan());
     if (s) return s;
-    s = launch_solve(b, x0, nullptr, nullptr, tol, max_iter, z_scratch, iters_scratch, st, nullptr,
-                     nullptr);
+    s = launch_solve(b, x0, nullptr, nullptr, tol, max_iter, z_scratch, nullptr, iters_scratch, st,
+                     nullptr, nullptr);
     if (s) return s;
     b->measured.assign(b->n_inst, 0);
     ADMM_HIP(hipMemcpyAsync(b->measured.data(), iters_scratch, sizeof(int32_t) * b->n_inst,
@@ -956,7 +1069,8 @@ admm_status admm_mpc_batch_tune(admm_mpc_batch* b, const float* x0, float tol, i
     if (s) { hipEventDestroy(e0); hipEventDestroy(e1); return s; }
     float tmin = 1e30f;
     for (int rep = 0; rep < std::max(1, reps); ++rep) {
-      s = launch_solve(b, x0, nullptr, nullptr, tol, max_iter, z_scratch, iters_scratch, st, e0, e1);
+      s = launch_solve(b, x0, nullptr, nullptr, tol, max_iter, z_scratch, nullptr, iters_scratch, st,
+                       e0, e1);
       if (s) { hipEventDestroy(e0); hipEventDestroy(e1); return s; }
       hipError_t he = hipEventSynchronize(e1);
       if (he != hipSuccess) { hipEventDestroy(e0); hipEventDestroy(e1); ADMM_HIP(he); }

@@ -33,6 +33,11 @@ def _setup():
     L.admm_mpc_batch_solve.restype = st
     L.admm_mpc_batch_solve.argtypes = [VP, VP, VP, ctypes.c_int32, ctypes.c_float,
                                        ctypes.c_int32, VP, VP, VP]
+    L.admm_mpc_batch_solve_state.restype = st
+    L.admm_mpc_batch_solve_state.argtypes = [VP, VP, VP, VP, ctypes.c_float, ctypes.c_int32,
+                                             VP, VP, VP, VP]
+    L.admm_mpc_batch_shift.restype = st
+    L.admm_mpc_batch_shift.argtypes = [VP, VP, VP, VP, VP, VP, VP, VP, VP]
     L.admm_mpc_batch_dual_complete.restype = st
     L.admm_mpc_batch_dual_complete.argtypes = [VP, VP, VP, VP]
     L.admm_mpc_batch_set_plan.restype = st
@@ -103,6 +108,20 @@ class MPCBatch:
         check(_setup().admm_mpc_batch_solve(self._h, _ptr(x0), _ptr(z_init), 1 if dual else 0,
                                             float(tol), int(max_iter), _ptr(z_out),
                                             _ptr(iters_out), _stream(stream)))
+
+    def solve_state(self, x0, z_out, iters_out, z_init=None, u_init=None, u_out=None,
+                    tol: float = 1e-4, max_iter: int = 10000, stream=None):
+        """Solve from (z_init, u_init) and return the final duals in u_out."""
+        check(_setup().admm_mpc_batch_solve_state(self._h, _ptr(x0), _ptr(z_init), _ptr(u_init),
+                                                  float(tol), int(max_iter), _ptr(z_out),
+                                                  _ptr(u_out), _ptr(iters_out), _stream(stream)))
+
+    def shift(self, x0, z, x0_next, z_next=None, u=None, u_next=None, w=None, stream=None):
+        """One receding-horizon step: x0_next = A x0 + B u_0 + w, and the
+        trajectory (and duals) moved one step forward."""
+        check(_setup().admm_mpc_batch_shift(self._h, _ptr(x0), _ptr(z), _ptr(u), _ptr(w),
+                                            _ptr(x0_next), _ptr(z_next), _ptr(u_next),
+                                            _stream(stream)))
 
     def dual_complete(self, z, u_out, stream=None):
         check(_setup().admm_mpc_batch_dual_complete(self._h, _ptr(z), _ptr(u_out),
