@@ -130,6 +130,61 @@ def bench_mpc_batch(torch):
                 instance_iterations_per_s=float(np.abs(its).sum()) / best)
 
 
+def bench_mpc_closed_loop(torch, cycles=8, sd=0.1):
+    """Receding-horizon control of the 4096-instance batch: each cycle the
+    plant applies the first planned input plus a disturbance w ~ N(0, sd^2)
+    (seed 1103), and the next solve to residual 1e-4 starts (a) from the
+    previous solution and duals moved one step forward (shift kernel
+    included in the time), (b) from the previous solution as it is, the new
+    x0 only, or (c) cold.  All three solve the same sequence of x0 (the one
+    that (a) produces)."""
+    import numpy as np
+    import workloads as W
+    from paper_1603_02526_amd import mpc as M
+    insts = W.mpc_batch(4096, seed=1003)
+    b = M.MPCBatch(insts)
+    x0 = torch.tensor(b.pack_x0([i.x0 for i in insts]), device="cuda")
+    zeros = lambda n: torch.zeros(int(n), device="cuda")
+    z, u, zn, un, zo, uo, zt = (zeros(b.z_total), zeros(b.u_total), zeros(b.z_total),
+                                zeros(b.u_total), zeros(b.z_total), zeros(b.u_total),
+                                zeros(b.z_total))
+    x0n = zeros(b.x0_total)
+    it = torch.zeros(b.n_inst, dtype=torch.int32, device="cuda")
+    b.tune(x0, zt, it, tol=1e-4, reps=1)
+    ws = torch.tensor(W.mpc_disturbance(b.x0_total, cycles, seed=1103, sd=sd), device="cuda")
+    b.solve_state(x0, z, it, u_out=u, tol=1e-4)
+    modes = ("shift", "noshift", "cold")
+    secs = {k: 0.0 for k in modes}
+    its = {k: [] for k in modes}
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    for c in range(cycles):
+        def shift_solve():
+            b.shift(x0, z, x0n, z_next=zn, u=u, u_next=un, w=ws[c])
+            b.solve_state(x0n, zo, it, z_init=zn, u_init=un, u_out=uo, tol=1e-4)
+        secs["shift"] += timed(shift_solve)
+        its["shift"].append(it.cpu().numpy())
+        secs["noshift"] += timed(lambda: b.solve_state(x0n, zt, it, z_init=z, u_init=u, tol=1e-4))
+        its["noshift"].append(it.cpu().numpy())
+        secs["cold"] += timed(lambda: b.solve_state(x0n, zt, it, tol=1e-4))
+        its["cold"].append(it.cpu().numpy())
+        x0, x0n = x0n, x0
+        z, zo = zo, z
+        u, uo = uo, u
+    n = 4096 * cycles
+    res = {k: dict(solves_per_s=n / secs[k], seconds=secs[k],
+                   iterations=_iter_stats(np.concatenate(its[k]))) for k in modes}
+    res.update(instances=4096, cycles=cycles, disturbance_sd=sd,
+               shift_over_cold=res["shift"]["solves_per_s"] / res["cold"]["solves_per_s"])
+    return res
+
+
 def bench_warmstart(torch, args):
     """Warm-start family: systems n=8, m=3, T=100 (seed 2000+s); per system an
     MLP 8 -> 256 -> 256 -> 1100 trained on GPU-solved x0 ~ N(0, I) (seed
@@ -309,6 +364,7 @@ def main():
 
     if not args.no_mpc:
         out.setdefault("secondary", {})["mpc_batch_4096"] = bench_mpc_batch(torch)
+        out["secondary"]["mpc_closed_loop_4096"] = bench_mpc_closed_loop(torch)
         out["secondary"]["mpc_warmstart"] = bench_warmstart(torch, args)
 
     if not args.no_cpu:

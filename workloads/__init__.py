@@ -286,6 +286,12 @@ def mpc_x0(n: int, count: int, seed: int) -> np.ndarray:
     return np.random.default_rng(seed).standard_normal((count, n))
 
 
+def mpc_disturbance(total: int, cycles: int, seed: int, sd: float = 0.1) -> np.ndarray:
+    """Plant disturbances of a closed loop, w ~ N(0, sd^2 I) per state entry
+    and cycle, shape [cycles, total] (float32)."""
+    return (sd * np.random.default_rng(seed).standard_normal((cycles, total))).astype(np.float32)
+
+
 def mpc_graph(inst: MPCInstance, box: bool = True) -> Problem:
     """Factor graph of one MPC instance.
 
