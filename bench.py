@@ -326,6 +326,20 @@ def main():
                                     ms_per_solve=s2 * 1e3, iterations=500,
                                     xpass_avg_us=x2 * 1e3 / 500,
                                     xpass_GBs=inf2["algo_bytes_per_iter"] / (x2 * 1e-3 / 500) / 1e9)
+        # the paper's own SVM graph on the same data: a copy of w per point
+        # tied by equality factors, margin and minimal-error factors
+        p3 = W.svm_copies(100_000, 20, seed=1002)
+        g3 = A.Graph.from_problem(p3, precision=A.FP32, device=0)
+        s3 = time_solve(g3, 500, 5, 1, torch, stream)
+        g3.set_state(p3.z0)
+        x3, z3 = g3.run_profiled(500, stream)
+        inf3 = g3.info()
+        secd["svm_copies_100k_d20"] = dict(edge_updates_per_s=p3.n_edges * 500 / s3,
+                                           slot_updates_per_s=p3.n_slots * 500 / s3,
+                                           ms_per_solve=s3 * 1e3, iterations=500,
+                                           edges=p3.n_edges, slots=p3.n_slots,
+                                           xpass_avg_us=x3 * 1e3 / 500, zpass_avg_us=z3 * 1e3 / 500,
+                                           xpass_GBs=inf3["algo_bytes_per_iter"] / (x3 * 1e-3 / 500) / 1e9)
         # the headline solve including the host transfers of the boundary:
         # z0 in (admm_set_state) and z out (admm_get_z), FP64 host arrays
         th = []

@@ -59,6 +59,13 @@ typedef enum {
  *  L2          any                       lambda (1)            App. C, lambda/2 |w|^2
  *  LINDYN      x(n) u(m) x'(n)           A (n*n) B (n*m)       App. B, x' = A x + B u
  *  LINDYN0     u(m) x'(n)                A B x0 (n*n+n*m+n)    App. B, x' = A x0 + B u
+ *  MINERR      any                       lambda (1)            App. C, lambda sum xi_k, xi_k >= 0
+ *  EQUAL       w1(d) w2(d)               none (0)              App. C, w1 = w2
+ *  MARGIN      w(d) b(1) xi(1)           x_1..x_d y (d+1)      App. C, y(w.x + b) >= 1 - xi
+ * MINERR requires lambda >= 0 and MARGIN y = +1 or -1, d <= 64 and the same
+ * d for every factor of one call.  MARGIN's prox is the projection onto
+ * its half-space (the appendix's closed form with the signs that make the
+ * output feasible: w += mu y x / rho, b += mu y / rho, xi += mu / rho).
  * Matrices are row-major.  The prox of NONOVERLAP moves the radii by -D/4
  * (the sign that makes the output feasible) and uses the direction (1,0)
  * when the two centres coincide; RADIUS requires rho > gamma. */
@@ -71,7 +78,10 @@ typedef enum {
   ADMM_F_HINGE = 6,
   ADMM_F_L2 = 7,
   ADMM_F_LINDYN = 8,
-  ADMM_F_LINDYN0 = 9
+  ADMM_F_LINDYN0 = 9,
+  ADMM_F_MINERR = 10,
+  ADMM_F_EQUAL = 11,
+  ADMM_F_MARGIN = 12
 } admm_factor_kind;
 
 typedef enum { ADMM_FP32 = 0, ADMM_FP64 = 1 } admm_precision;

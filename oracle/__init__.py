@@ -24,7 +24,7 @@ LIB_PATH = os.path.join(HERE, "liboracle.so")
 SRC = os.path.join(HERE, "admm_oracle.cpp")
 
 KIND = dict(nonoverlap=1, wall=2, radius=3, quad=4, box=5, hinge=6, l2=7,
-            lindyn=8, lindyn0=9)
+            lindyn=8, lindyn0=9, minerr=10, equal=11, margin=12)
 
 
 def build(force: bool = False) -> str:

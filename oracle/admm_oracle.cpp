@@ -35,6 +35,13 @@
 //   hinge       f = C max(0, 1 - y(w.a + b)), the minimal-error and margin
 //               POs of App. C merged into one factor per point.
 //   l2          f = lambda/2 |w|^2 (App. C, norm-two PO).
+//   minerr      f = lambda sum xi_k with xi_k >= 0 (App. C, minimal-error
+//               PO): xi = (n - lambda/rho)^+.
+//   equal       w1 = w2 (App. C, equality PO): both take the mean.
+//   margin      projection onto y(w.x + b) >= 1 - xi (App. C, one-point
+//               margin PO).  The printed closed form has a garbled product
+//               and signs that leave the output infeasible; the projection
+//               is rederived from its Lagrange conditions.
 //
 // Stopping measures (the paper leaves them open): after the u-update,
 //   r = max_e |x_e - z_b|        s = rho * max_b |z_b - z_b(previous)|.
@@ -57,6 +64,9 @@ enum Kind {
   K_L2 = 7,
   K_LINDYN = 8,
   K_LINDYN0 = 9,
+  K_MINERR = 10,
+  K_EQUAL = 11,
+  K_MARGIN = 12,
 };
 
 struct Factor {
@@ -179,6 +189,40 @@ void prox_l2(const double* nv, int k, double lam, double rho, double* out) {
   for (int i = 0; i < k; ++i) out[i] = rho * nv[i] / (rho + lam);
 }
 
+// lambda sum xi_k over xi_k >= 0: a shifted clamp at zero.
+void prox_minerr(const double* nv, int k, double lam, double rho, double* out) {
+  for (int i = 0; i < k; ++i) out[i] = std::max(0.0, nv[i] - lam / rho);
+}
+
+// w1 = w2 with equal weights on both edges: the nearest point of the
+// diagonal is the mean of the two inputs.
+void prox_equal(const double* nv, int d, double* out) {
+  for (int i = 0; i < d; ++i) {
+    const double v = 0.5 * (nv[i] + nv[d + i]);
+    out[i] = v;
+    out[d + i] = v;
+  }
+}
+
+// Edges (w (d), b, xi), p = (x_1..x_d, y).  minimise rho/2 |(w,b,xi) - n|^2
+// subject to y(w.x + b) + xi >= 1.  If n satisfies the constraint it is its
+// own projection.  Otherwise the constraint is active with multiplier
+// mu >= 0: w = n_w + mu y x / rho, b = n_b + mu y / rho, xi = n_xi + mu / rho,
+// and substituting into the active constraint (y^2 = 1) gives
+// mu = (1 - g0) / ((|x|^2 + 2) / rho) with g0 = y(n_w.x + n_b) + n_xi.
+void prox_margin(const double* nv, int d, const double* p, double rho, double* out) {
+  const double y = p[d];
+  double wx = 0.0, xx = 0.0;
+  for (int k = 0; k < d; ++k) { wx += nv[k] * p[k]; xx += p[k] * p[k]; }
+  const double g0 = y * (wx + nv[d]) + nv[d + 1];
+  for (int k = 0; k < d + 2; ++k) out[k] = nv[k];
+  if (g0 >= 1.0) return;
+  const double mu = (1.0 - g0) / ((xx + 2.0) / rho);
+  for (int k = 0; k < d; ++k) out[k] = nv[k] + mu * y * p[k] / rho;
+  out[d] = nv[d] + mu * y / rho;
+  out[d + 1] = nv[d + 1] + mu / rho;
+}
+
 // Projection onto x' = A x + B u on edges (x, u, x') with A n x n, B n x m
 // (row-major).  Minimise |a - a_n|^2 + |M a - b|^2 with a = (x, u),
 // M = [A B], b = n_x': normal equations (I + M^T M) a = a_n + M^T b.
@@ -289,6 +333,24 @@ int prox_apply(int kind, int arity, const int* dims, const double* p, int plen,
       for (int e = 0; e < arity; ++e) k += dims[e];
       if (plen != 1) return -1;
       prox_l2(nv, k, p[0], rho, out);
+      return 0;
+    }
+    case K_MINERR: {
+      int k = 0;
+      for (int e = 0; e < arity; ++e) k += dims[e];
+      if (plen != 1 || !(p[0] >= 0.0)) return -1;
+      prox_minerr(nv, k, p[0], rho, out);
+      return 0;
+    }
+    case K_EQUAL:
+      if (arity != 2 || dims[0] != dims[1] || plen != 0) return -1;
+      prox_equal(nv, dims[0], out);
+      return 0;
+    case K_MARGIN: {
+      if (arity != 3 || dims[1] != 1 || dims[2] != 1) return -1;
+      const int d = dims[0];
+      if (plen != d + 1 || (p[d] != 1.0 && p[d] != -1.0)) return -1;
+      prox_margin(nv, d, p, rho, out);
       return 0;
     }
     case K_LINDYN: {

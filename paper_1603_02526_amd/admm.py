@@ -21,7 +21,7 @@ STATUS_NAMES = {0: "OK", 1: "E_ARG", 2: "E_STATE", 3: "E_NUMERIC", 4: "E_HIP",
                 5: "E_OOM", 6: "E_NO_DEVICE", 7: "E_UNSUPPORTED"}
 
 KIND = dict(nonoverlap=1, wall=2, radius=3, quad=4, box=5, hinge=6, l2=7,
-            lindyn=8, lindyn0=9)
+            lindyn=8, lindyn0=9, minerr=10, equal=11, margin=12)
 FP32, FP64 = 0, 1
 OPT_PAIR_ROWS, OPT_DRIVER, OPT_PAIR_STATE = 1, 2, 3
 DRIVER_AUTO, DRIVER_LAUNCHES, DRIVER_RESIDENT = 0, 1, 2

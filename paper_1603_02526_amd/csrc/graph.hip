@@ -152,6 +152,29 @@ int32_t kind_dim_ok(const admm_graph& g, const Group& gr, std::string& why, int3
     case KD_L2:
       if (gr.plen != 1) { why = "L2 needs 1 param"; return 0; }
       return 1;
+    case KD_MINERR:
+      if (gr.plen != 1) { why = "MINERR needs 1 param"; return 0; }
+      for (int64_t f = 0; f < gr.n; ++f)
+        if (!(gr.prm(f)[0] >= 0.0)) { why = "MINERR needs lambda >= 0"; return 0; }
+      return 1;
+    case KD_EQUAL:
+      if (A != 2 || gr.plen != 0) { why = "EQUAL needs arity 2 and no params"; return 0; }
+      for (int64_t f = 0; f < gr.n; ++f)
+        if (D(f, 0) != D(f, 1)) { why = "EQUAL edges must have equal dims"; return 0; }
+      return 1;
+    case KD_MARGIN: {
+      if (A != 3) { why = "MARGIN needs arity 3 (w, b, xi)"; return 0; }
+      const int d = gr.n > 0 ? D(0, 0) : 0;
+      if (gr.plen != d + 1) { why = "MARGIN needs d+1 params (x_1..x_d, y)"; return 0; }
+      for (int64_t f = 0; f < gr.n; ++f) {
+        if (D(f, 0) != d || D(f, 1) != 1 || D(f, 2) != 1) {
+          why = "MARGIN edges must have dims (d,1,1), d the same within one call"; return 0;
+        }
+        const double y = gr.prm(f)[d];
+        if (y != 1.0 && y != -1.0) { why = "MARGIN needs y = +1 or -1"; return 0; }
+      }
+      return 1;
+    }
     case KD_LINDYN:
     case KD_LINDYN0: {
       const bool first = gr.kind == KD_LINDYN0;
@@ -284,7 +307,7 @@ admm_status build_plan(admm_graph& g, Plan& P, bool no_tiles) {
 
     std::vector<int32_t> ezc, ezr, fe1, fe2;
     const bool separable = gr.kind == KD_RADIUS || gr.kind == KD_QUAD || gr.kind == KD_BOX ||
-                           gr.kind == KD_L2;
+                           gr.kind == KD_L2 || gr.kind == KD_MINERR;
     if (gr.kind == KD_NONOVERLAP && !P.no_tiles &&
         detect_complete_pairs(g, gr, ezc, ezr, fe1, fe2)) {
       // ---------------- dense pair tiles ----------------
@@ -405,6 +428,89 @@ admm_status build_plan(admm_graph& g, Plan& P, bool no_tiles) {
           ++us;
         }
       P.algo_elems += (int64_t)gr.n * (2 * gr.arity + d + 3);
+    } else if (gr.kind == KD_EQUAL) {
+      // ---------------- equality: one thread per component pair ----------------
+      b.mode = BM_GEN_FACTOR;
+      b.arity = 2;
+      b.nslot = 2;
+      int64_t np = 0;
+      for (int64_t f = 0; f < gr.n; ++f) np += g.dim[gr.vids[f * 2]];
+      b.n = np;
+      b.nfp = round_up(np, 64);
+      const int64_t i0 = (int64_t)P.idx.size();
+      P.idx.resize(i0 + 2 * b.nfp, 0);
+      P.n_m += 2 * b.nfp;
+      b.dst_off = (int64_t)P.idx.size();
+      P.idx.resize(P.idx.size() + 2 * b.nfp, -1);
+      int64_t j = 0;
+      for (int64_t f = 0; f < gr.n; ++f) {
+        const int dm = g.dim[gr.vids[f * 2]];
+        for (int e = 0; e < 2; ++e)
+          for (int c = 0; c < dm; ++c) {
+            const int64_t zi = zof(f, e) + c;
+            P.idx[i0 + e * b.nfp + j + c] = (int32_t)zi;
+            P.upos[us] = b.m_off + (int64_t)e * b.nfp + j + c;
+            P.uz[us] = (int32_t)zi;
+            deg[zi]++;
+            ++us;
+            em.push_back({zi, b.dst_off + (int64_t)e * b.nfp + j + c});
+          }
+        j += dm;
+      }
+      b.blk0 = (int32_t)blocks;
+      blocks += (np + NT - 1) / NT;
+      b.blk1 = (int32_t)blocks;
+      P.algo_elems += 4 * np;
+      P.layout_idx_bytes += 2 * np * 4;
+    } else if (gr.kind == KD_MARGIN) {
+      // ---------------- margin: the general hinge path with a slack slot ----------------
+      b.mode = BM_GEN_FACTOR;
+      b.n = gr.n;
+      b.nfp = round_up(gr.n, 64);
+      const int d = g.dim[gr.vids[0]];
+      b.d = d;
+      if (d > 64) return admmi::set_err(ADMM_E_UNSUPPORTED, "MARGIN with d > 64 is not supported");
+      b.dmax = d <= 32 ? 32 : 64;
+      b.nslot = d + 2;
+      const int64_t i0 = (int64_t)P.idx.size();
+      P.idx.resize(i0 + (int64_t)(d + 2) * b.nfp, 0);
+      P.par.resize(P.par.size() + (size_t)(d + 3) * b.nfp, 0.0);
+      double* par = P.par.data() + b.par_off;
+      for (int64_t f = 0; f < gr.n; ++f) {
+        for (int k = 0; k < d; ++k) P.idx[i0 + k * b.nfp + f] = (int32_t)(zof(f, 0) + k);
+        P.idx[i0 + d * b.nfp + f] = (int32_t)zof(f, 1);
+        P.idx[i0 + (d + 1) * b.nfp + f] = (int32_t)zof(f, 2);
+        const double* p = gr.prm(f);
+        const double y = p[d];
+        double xx = 0.0;
+        for (int k = 0; k < d; ++k) { par[k * b.nfp + f] = y * p[k]; xx += p[k] * p[k]; }
+        par[d * b.nfp + f] = y;
+        par[(d + 1) * b.nfp + f] = INFINITY;
+        par[(d + 2) * b.nfp + f] = g.rho / (xx + 2.0);
+      }
+      P.n_m += (int64_t)b.nslot * b.nfp;
+      b.dst_off = (int64_t)P.idx.size();
+      P.idx.resize(P.idx.size() + (int64_t)b.nslot * b.nfp, -1);
+      // one bias for every factor (the usual graph): one partial per workgroup
+      b.ub = 1;
+      for (int64_t f = 1; f < gr.n && b.ub; ++f) b.ub = zof(f, 1) == zof(0, 1);
+      const int64_t tiles = (gr.n + NT - 1) / NT;
+      for (int64_t f = 0; f < gr.n; ++f)
+        for (int s = 0; s < d + 2; ++s) {
+          const int64_t zi = P.idx[i0 + s * b.nfp + f];
+          P.upos[us] = b.m_off + (int64_t)s * b.nfp + f;
+          P.uz[us] = (int32_t)zi;
+          deg[zi]++;
+          ++us;
+          if (!(b.ub && s == d)) em.push_back({zi, b.dst_off + (int64_t)s * b.nfp + f});
+        }
+      if (b.ub)
+        for (int64_t t = 0; t < tiles; ++t) em.push_back({zof(0, 1), b.dst_off + (int64_t)d * b.nfp + t});
+      b.blk0 = (int32_t)blocks;
+      blocks += tiles;
+      b.blk1 = (int32_t)blocks;
+      P.algo_elems += (int64_t)gr.n * (2 * b.nslot + d + 3);
+      P.layout_idx_bytes += (int64_t)gr.n * b.nslot * 4;
     } else if (separable) {
       // ---------------- separable operators: one thread per slot ----------------
       b.mode = BM_GEN_SLOT;
@@ -434,6 +540,7 @@ admm_status build_plan(admm_graph& g, Plan& P, bool no_tiles) {
               case KD_QUAD: p0 = g.rho / (g.rho + p[comp]); break;
               case KD_L2: p0 = g.rho / (g.rho + p[0]); break;
               case KD_BOX: p0 = p[0]; p1 = p[1]; break;
+              case KD_MINERR: p0 = p[0] / g.rho; break;
             }
             par[s] = p0;
             par[b.nfp + s] = p1;
@@ -805,7 +912,9 @@ struct Engine : EngineBase {
       for (const BucketDesc& b : P.bt) {
         if (b.mode == BM_PAIR) need |= b.sparse ? FT_PAIRSP : FT_PAIR;
         else if (b.mode == BM_UNIF_HINGE && b.dmax <= 32) need |= FT_UHINGE;
-        else if (b.mode == BM_GEN_SLOT || b.kind == KD_NONOVERLAP || b.kind == KD_WALL) need |= FT_GEN;
+        else if (b.mode == BM_GEN_SLOT || b.kind == KD_NONOVERLAP || b.kind == KD_WALL ||
+                 b.kind == KD_EQUAL)
+          need |= FT_GEN;
         else need |= FT_WIDE;
       }
       fs = ((need & ~FS_PAIR) == 0)     ? FS_PAIR
@@ -1143,7 +1252,7 @@ admm_status admm_graph_add_factors(admm_graph* g, int32_t kind, int32_t n_factor
   admmi::clear_err();
   if (admm_status s = check_graph(g)) return s;
   if (g->state != 0) return admmi::set_err(ADMM_E_STATE, "graph already finalized");
-  if (kind < KD_NONOVERLAP || kind > KD_LINDYN0) return admmi::set_err(ADMM_E_ARG, "unknown factor kind %d", kind);
+  if (kind < KD_NONOVERLAP || kind > KD_MARGIN) return admmi::set_err(ADMM_E_ARG, "unknown factor kind %d", kind);
   if (n_factors < 0 || arity < 1 || param_len < 0) return admmi::set_err(ADMM_E_ARG, "bad sizes");
   if (n_factors > 0 && !var_ids) return admmi::set_err(ADMM_E_ARG, "var_ids is NULL");
   if (param_len > 0 && !params) return admmi::set_err(ADMM_E_ARG, "params is NULL");

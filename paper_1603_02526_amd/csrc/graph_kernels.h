@@ -41,6 +41,7 @@ enum PassMode : int { PM_NORMAL = 0, PM_SAVE = 1, PM_RESID = 2 };
 enum Kind : int32_t {
   KD_NONOVERLAP = 1, KD_WALL = 2, KD_RADIUS = 3, KD_QUAD = 4, KD_BOX = 5,
   KD_HINGE = 6, KD_L2 = 7, KD_LINDYN = 8, KD_LINDYN0 = 9,
+  KD_MINERR = 10, KD_EQUAL = 11, KD_MARGIN = 12,
 };
 
 // Descriptor of one bucket, read by the x-pass from device memory.
@@ -57,6 +58,9 @@ struct BucketDesc {
   int64_t flag0;        // pair layout: first flag word of this bucket (per tile NT words)
   int32_t ent_aff;      // pair layout: entity e's z offsets are ent_base + 3e (centre), + 2 (radius)
   int32_t ent_base;
+  int32_t ub;           // hinge/margin: the b edge is one variable for every factor
+                        // of the bucket, which takes one partial sum per workgroup
+  int32_t ub_pad;
   int64_t m_off, x_off;  // element offsets of the state regions in the pool
   int64_t dst_off;      // index-buffer offset of the contribution destinations
   int64_t idx_off;      // offset in the int32 index buffer
@@ -758,6 +762,9 @@ __device__ __forceinline__ void xpass_pair_sparse(const XArgs<float>& a, const B
 // UNIF: every factor shares the variable list (z offsets [d+1]); each
 // workgroup of 256 factors emits column partials [tile][d+1].
 // Otherwise z offsets are per edge [d+1][nfp] and m itself is summed.
+// MARGIN (App. C, one-point margin, sign-corrected): the same projection
+// onto y(w.x + b) + xi >= 1 with the slack xi as slot d+1, no upper bound
+// (C = +inf) and rho/(|x|^2+2) as the last parameter.
 // ---------------------------------------------------------------------------
 template <typename T, bool A1, int MODE, bool UNIF, int DM>
 __device__ __forceinline__ void xpass_hinge(const XArgs<T>& a, const BucketDesc& b, int blk) {
@@ -795,8 +802,16 @@ __device__ __forceinline__ void xpass_hinge(const XArgs<T>& a, const BucketDesc&
   const T mb = M[d * nfp + ff];
   T xob = T(0);
   if constexpr (!A1 || MODE == PM_RESID) xob = X[d * nfp + ff];
+  const bool margin = !UNIF && b.kind == KD_MARGIN;
+  T zs = T(0), ms = T(0), xos = T(0);
+  if (margin) {
+    zs = a.z[zo[(d + 1) * nfp + ff]];
+    ms = M[(d + 1) * nfp + ff];
+    if constexpr (!A1 || MODE == PM_RESID) xos = X[(d + 1) * nfp + ff];
+  }
   if constexpr (MODE == PM_RESID) {
     if (valid) rmax = tmax(rmax, tabs(xob - zb));
+    if (valid && margin) rmax = tmax(rmax, tabs(xos - zs));
     block_max_store(rmax, a.blockmax);
     return;
   } else {
@@ -804,14 +819,28 @@ __device__ __forceinline__ void xpass_hinge(const XArgs<T>& a, const BucketDesc&
     state_un<T, A1>(mb, xob, zb, a.alpha, ub, nb);
     const T y = P[d * nfp + ff], C = P[(d + 1) * nfp + ff], iD = P[(d + 2) * nfp + ff];
     dot += y * nb;
+    T us = T(0), ns = T(0);
+    if (margin) {
+      state_un<T, A1>(ms, xos, zs, a.alpha, us, ns);
+      dot += ns;
+    }
     const T tau = tmin(C, tmax(T(0), (T(1) - dot) * iD));
     const T st = tau * a.inv_rho;
     const T xb = nb + st * y;
     const T mnb = xb + ub;
+    const bool shared_b = !UNIF && b.ub;
     if (valid) {
       M[d * nfp + ff] = mnb;
       if constexpr (!A1 || MODE == PM_SAVE) X[d * nfp + ff] = xb;
-      if constexpr (!UNIF) a.pool[a.idx[b.dst_off + d * nfp + ff]] = mnb;
+      if constexpr (!UNIF) {
+        if (!shared_b) a.pool[a.idx[b.dst_off + d * nfp + ff]] = mnb;
+      }
+      if (margin) {
+        const T xs = ns + st;
+        M[(d + 1) * nfp + ff] = xs + us;
+        if constexpr (!A1 || MODE == PM_SAVE) X[(d + 1) * nfp + ff] = xs;
+        a.pool[a.idx[b.dst_off + (d + 1) * nfp + ff]] = xs + us;
+      }
     }
 #pragma unroll
     for (int k = 0; k < DM; ++k) {
@@ -827,6 +856,18 @@ __device__ __forceinline__ void xpass_hinge(const XArgs<T>& a, const BucketDesc&
           const T s = admmi::wave_sum(valid ? mk : T(0));
           if (lane == 0) wsum[w][k] = s;
         }
+      }
+    }
+    if (shared_b) {
+      // the shared b edge: this workgroup's sum of m in a fixed order
+      const T sb = admmi::wave_sum(valid ? mnb : T(0));
+      if (lane == 0) wsum[w][0] = sb;
+      __syncthreads();
+      if (t == 0) {
+        T acc = wsum[0][0];
+#pragma unroll
+        for (int q = 1; q < NT / 64; ++q) acc += wsum[q][0];
+        a.pool[a.idx[b.dst_off + d * nfp + blk]] = acc;
       }
     }
     if constexpr (UNIF) {
@@ -849,6 +890,7 @@ __device__ __forceinline__ void xpass_hinge(const XArgs<T>& a, const BucketDesc&
 //   QUAD    x = p0 n,         p0 = rho/(rho + q_k)
 //   L2      x = p0 n,         p0 = rho/(rho + lambda)
 //   BOX     x = min(p1, max(p0, n)), (p0, p1) = (lo, hi)
+//   MINERR  x = max(0, n - p0),  p0 = lambda/rho  (App. C, minimal error)
 // ---------------------------------------------------------------------------
 template <typename T, bool A1, int MODE>
 __device__ __forceinline__ void xpass_slot(const XArgs<T>& a, const BucketDesc& b, int blk) {
@@ -873,6 +915,8 @@ __device__ __forceinline__ void xpass_slot(const XArgs<T>& a, const BucketDesc& 
         x = tmin(P[b.nfp + s], tmax(p0, n));
       } else if (b.kind == KD_RADIUS) {
         x = tmax(T(0), p0 * n);
+      } else if (b.kind == KD_MINERR) {
+        x = tmax(T(0), n - p0);
       } else {
         x = p0 * n;
       }
@@ -937,13 +981,25 @@ __device__ __forceinline__ void gen_store(const XArgs<T>& a, const BucketDesc& b
   }
 }
 
-// Non-overlap and wall factors on arbitrary variables.
+// Non-overlap and wall factors on arbitrary variables, and equality
+// factors split into scalar component pairs (App. C: with equal weights
+// both copies take the mean of the pair).
 template <typename T, bool A1, int MODE>
 __device__ __forceinline__ void xpass_geom(const XArgs<T>& a, const BucketDesc& b, int blk) {
   const int64_t f = (int64_t)blk * NT + threadIdx.x;
   T rmax = T(0);
   if (f < b.n) {
-    if (b.kind == KD_NONOVERLAP) {
+    if (b.kind == KD_EQUAL) {
+      const int dims[4] = {1, 1, 0, 0};
+      T u[2], v[2];
+      gen_gather<T, A1, MODE, 2>(a, b, f, dims, 2, u, v, rmax);
+      if constexpr (MODE != PM_RESID) {
+        const T mean = (v[0] + v[1]) * T(0.5);
+        v[0] = mean;
+        v[1] = mean;
+        gen_store<T, A1, MODE, 2>(a, b, f, u, v);
+      }
+    } else if (b.kind == KD_NONOVERLAP) {
       const int dims[4] = {2, 1, 2, 1};
       T u[6], v[6];
       gen_gather<T, A1, MODE, 6>(a, b, f, dims, 4, u, v, rmax);
@@ -1130,10 +1186,10 @@ __device__ __forceinline__ void xpass_block(XArgs<T> a, int blk) {
       xpass_hinge<T, A1, MODE, true, 64>(a, b, local);
   } else if ((FS & FT_GEN) && b.mode == BM_GEN_SLOT) {
     xpass_slot<T, A1, MODE>(a, b, local);
-  } else if ((FS & FT_GEN) && (b.kind == KD_NONOVERLAP || b.kind == KD_WALL)) {
+  } else if ((FS & FT_GEN) && (b.kind == KD_NONOVERLAP || b.kind == KD_WALL || b.kind == KD_EQUAL)) {
     xpass_geom<T, A1, MODE>(a, b, local);
   } else if (FS & FT_WIDE) {
-    if (b.kind == KD_HINGE) {
+    if (b.kind == KD_HINGE || b.kind == KD_MARGIN) {
       if (b.dmax <= 32)
         xpass_hinge<T, A1, MODE, false, 32>(a, b, local);
       else

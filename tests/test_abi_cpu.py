@@ -116,6 +116,20 @@ def test_svm_layout():
     assert inf["n_contributions"] == 20 * 21 + 20
 
 
+def test_copies_svm_layout():
+    N, d = 3000, 20
+    p = W.svm_copies(N, d, seed=4)
+    g = A.Graph.from_problem(p, device=None)
+    assert _finalize_cpu(g) in (A.OK, A.E_NO_DEVICE)
+    inf = g.info()
+    assert inf["n_edges"] == p.n_edges and inf["n_slots"] == p.n_slots
+    # margin, minimal-error, norm and equality buckets
+    assert inf["n_buckets"] == 4
+    # every slot contributes its m directly, except the shared bias: one
+    # partial per 256-factor workgroup of the margin bucket
+    assert inf["n_contributions"] == p.n_slots - N + (N + 255) // 256
+
+
 def test_incomplete_pairs_fall_back_to_general_layout():
     p = W.packing(12, "square", 0.05, seed=2)
     g0 = p.groups[0]
@@ -146,6 +160,12 @@ def test_validation_errors():
     _expect(A.E_ARG, g.add_factors, "quad", [[0]], [[1.0, 2.0]])          # weight short
     g = A.Graph([3])
     _expect(A.E_ARG, g.add_factors, "box", [[0]], [1.0, -1.0], True)     # lo > hi
+    g = A.Graph([2, 1, 1])
+    _expect(A.E_ARG, g.add_factors, "margin", [[0, 1, 2]], [[1.0, 2.0, 0.5]])   # y not +-1
+    _expect(A.E_ARG, g.add_factors, "margin", [[0, 1, 2]], [[1.0, 1.0]])        # param_len
+    _expect(A.E_ARG, g.add_factors, "margin", [[1, 0, 2]], [[1.0, 1.0]])        # dims (1,2,1)
+    _expect(A.E_ARG, g.add_factors, "equal", [[0, 1]])                          # dims 2 vs 1
+    _expect(A.E_ARG, g.add_factors, "minerr", [[1]], [-1.0], True)              # lambda < 0
     _expect(A.E_ARG, A.Graph, [1, 0])                                      # dim 0
     _expect(A.E_ARG, A.Graph, [1], 7)                                      # precision
     g = A.Graph([1])

@@ -131,6 +131,39 @@ def test_tiny_svm_kkt_and_qp(N, d, seed):
     np.testing.assert_allclose(w, w_ref, atol=1e-5)
 
 
+@pytest.mark.parametrize("N,d,seed", [(6, 2, 81), (8, 3, 82), (5, 2, 83)])
+def test_copies_svm_graph_reaches_the_hinge_optimum(N, d, seed):
+    """The paper's SVM graph (a copy of w per point tied by equality factors,
+    margin, minimal-error and 1/N-weighted norm factors) solves the same
+    problem as the hinge graph: at convergence every copy equals the
+    hinge graph's w, b agrees, the slacks are the hinge losses, and w is the
+    primal QP's minimiser."""
+    p = W.svm_copies(N, d, seed=seed, sep=1.0)
+    g = O.OracleGraph(p)
+    g.run(400000, tol=1e-13)
+    z = g.z
+    Wc = z[:N * d].reshape(N, d)
+    b, xi = z[N * d], z[N * d + 1:]
+    h = O.OracleGraph(W.svm(N, d, seed=seed, sep=1.0))
+    h.run(400000, tol=1e-13)
+    for i in range(N):
+        np.testing.assert_allclose(Wc[i], h.z[:d], atol=1e-7)
+    assert abs(b - h.z[d]) < 1e-7
+    a, y = p.meta["a"], p.meta["y"]
+    np.testing.assert_allclose(xi, np.maximum(0.0, 1.0 - y * (a @ Wc[0] + b)), atol=1e-7)
+    w_ref, _, _ = pins.svm_primal_slsqp(a, y, p.meta["C"])
+    np.testing.assert_allclose(Wc[0], w_ref, atol=1e-5)
+
+
+def test_copies_svm_graph_counts():
+    N, d = 7, 3
+    p = W.svm_copies(N, d, seed=84)
+    assert p.n_vars == 2 * N + 1
+    assert p.n_factors == 3 * N + (N - 1)
+    assert p.n_edges == 3 * N + N + N + 2 * (N - 1)
+    assert p.n_slots == N * (d + 2) + N + N * d + 2 * d * (N - 1)
+
+
 def test_fig1_edge_order():
     """Edge arrays follow edge creation: for f1(w1,w2,w3) + f2(w1,w4,w5) +
     f3(w2,w5) + f4(w5) the order is (1,1),(1,2),(1,3),(2,1),(2,4),(2,5),

@@ -132,6 +132,63 @@ def test_hinge_vs_slack_qp(rho):
         np.testing.assert_allclose(x, s[:-1], atol=2e-6)
 
 
+@pytest.mark.parametrize("rho", RHO)
+def test_minerr_vs_scan(rho):
+    """App. C minimal-error PO: argmin lambda xi + rho/2 (xi - n)^2, xi >= 0,
+    per component, against a fine scan of the one-dimensional objective."""
+    rng = np.random.default_rng(15)
+    lam = 0.7
+    nv = rng.standard_normal(7)
+    x = O.prox("minerr", [7], [lam], rho, nv)
+    grid = np.linspace(0.0, 4.0, 400001)
+    for xi, ni in zip(x, nv):
+        f = lam * grid + 0.5 * rho * (grid - ni) ** 2
+        assert abs(xi - grid[np.argmin(f)]) < 2e-5
+    with pytest.raises(Exception):
+        O.prox("minerr", [1], [-1.0], rho, [0.3])
+
+
+@pytest.mark.parametrize("rho", RHO)
+def test_equal_vs_least_squares(rho):
+    """App. C equality PO: min |w1 - n1|^2 + |w2 - n2|^2 over w1 = w2, solved
+    as an overdetermined least-squares problem in the shared vector."""
+    rng = np.random.default_rng(16)
+    d = 5
+    nv = rng.standard_normal(2 * d)
+    x = O.prox("equal", [d, d], [], rho, nv)
+    t, *_ = np.linalg.lstsq(np.vstack([np.eye(d), np.eye(d)]), nv, rcond=None)
+    np.testing.assert_allclose(x, np.r_[t, t], atol=1e-14)
+
+
+@pytest.mark.parametrize("rho", RHO)
+def test_margin_vs_constrained_minimum(rho):
+    """App. C one-point margin PO: the projection of (w, b, xi) onto
+    y(w.x + b) >= 1 - xi.  Feasible inputs are returned unchanged, the
+    output is feasible (active when the input was not) and SLSQP finds no
+    closer feasible point."""
+    rng = np.random.default_rng(17)
+    d = 4
+    active = 0
+    for _ in range(40):
+        xv = rng.standard_normal(d)
+        y = rng.choice([-1.0, 1.0])
+        nv = rng.standard_normal(d + 2) * 0.8
+        out = O.prox("margin", [d, 1, 1], np.r_[xv, y], rho, nv)
+
+        def g(v):
+            return y * (v[:d] @ xv + v[d]) + v[d + 1] - 1.0
+        if g(nv) >= 0:
+            np.testing.assert_array_equal(out, nv)
+            continue
+        active += 1
+        assert abs(g(out)) < 1e-12
+        s, _ = pins.slsqp(lambda v: _sq(v, nv), nv.copy(), [dict(type="ineq", fun=g)])
+        np.testing.assert_allclose(out, s, atol=2e-6)
+    assert active > 5
+    with pytest.raises(Exception):
+        O.prox("margin", [d, 1, 1], np.r_[np.ones(d), 0.5], 1.0, np.zeros(d + 2))
+
+
 def _lindyn_kkt(nv, n, m, A, B):
     """min |(x,u,x') - nv|^2 s.t. x' - A x - B u = 0 as one KKT system."""
     k = 2 * n + m

@@ -31,7 +31,7 @@ from typing import Dict, List, Optional
 import numpy as np
 
 KINDS = ("nonoverlap", "wall", "radius", "quad", "box", "hinge", "l2",
-         "lindyn", "lindyn0")
+         "lindyn", "lindyn0", "minerr", "equal", "margin")
 
 
 @dataclasses.dataclass
@@ -222,6 +222,38 @@ def svm(n_points: int, d: int = 20, seed: int = 1002, C: float = 1.0,
                    z0=np.zeros(d + 1), rho=rho, alpha=alpha,
                    meta=dict(a=a, y=y, C=C, d=d, seed=seed,
                              l2_weight=l2_weight))
+
+
+def svm_copies(n_points: int, d: int = 20, seed: int = 1002, lam: float = 1.0,
+               rho: float = 1.0, alpha: float = 1.0, sep: float = 0.5) -> Problem:
+    """The paper's own SVM graph (Sec. V-C): one copy ``w_i`` (dim d) of the
+    weight vector per point, the bias ``b`` and one slack ``xi_i`` per point.
+
+    Variable ids: ``w_i = i`` (dim d), ``b = N`` (dim 1), ``xi_i = N + 1 + i``
+    (dim 1).  Factors, in this order: one margin factor per point on
+    (w_i, b, xi_i) with data (a_i, y_i); one minimal-error factor per slack
+    (weight ``lam``); one squared-norm factor per copy with weight 1/N (the
+    1/2 |w|^2 term split into N equal parts); equality factors joining
+    consecutive copies (w_i, w_{i+1}), a chain (the paper's figure is not
+    available; a chain keeps every copy's degree at most four).  At
+    consensus the objective is 1/2 |w|^2 + lam sum xi_i subject to the
+    margins, the problem ``svm`` states with hinge factors and C = lam."""
+    a, y = svm_data(n_points, d, seed, sep)
+    N = int(n_points)
+    dims = np.concatenate([np.full(N, d, np.int32), np.ones(1 + N, np.int32)])
+    i = np.arange(N, dtype=np.int32)
+    groups = [
+        FactorGroup("margin", np.stack([i, np.full(N, N, np.int32), N + 1 + i], axis=1),
+                    np.concatenate([a, y[:, None]], axis=1)),
+        FactorGroup("minerr", (N + 1 + i)[:, None], np.array([lam], np.float64), shared=True),
+        FactorGroup("l2", i[:, None], np.array([1.0 / N], np.float64), shared=True),
+    ]
+    if N > 1:
+        groups.append(FactorGroup("equal", np.stack([i[:-1], i[1:]], axis=1),
+                                  np.zeros((0,), np.float64), shared=True))
+    return Problem(name=f"svm_copies_{N}x{d}", var_dims=dims, groups=groups,
+                   z0=np.zeros(int(dims.sum())), rho=rho, alpha=alpha,
+                   meta=dict(a=a, y=y, C=lam, d=d, seed=seed))
 
 
 # ----------------------------------------------------------------------------
