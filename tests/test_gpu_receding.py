@@ -194,3 +194,40 @@ def test_argument_errors():
         b.shift(x0, z, x0)                                   # x0_next is x0
     with pytest.raises(AdmmError):
         b.shift(x0, z, _zeros(b.x0_total), u=u)              # u without u_next
+
+
+def test_full_batch_cycle_from_common_state():
+    """One controller cycle of the benchmark's 4096-instance batch, checked
+    on sampled instances from a common state: the oracle takes the GPU's
+    cycle-0 solution and duals, applies its own shift with the same
+    disturbance and solves to the same tolerance."""
+    M = _mpc()
+    insts = W.mpc_batch(4096, seed=1003)
+    b = M.MPCBatch(insts)
+    x0 = _dev(b.pack_x0([i.x0 for i in insts]))
+    z, u, it = _zeros(b.z_total), _zeros(b.u_total), _zeros(b.n_inst, torch.int32)
+    b.solve_state(x0, z, it, u_out=u, tol=1e-4, max_iter=10000)
+    w = W.mpc_disturbance(b.x0_total, 1, seed=1103, sd=0.1)[0]
+    x0n, zn, un = _zeros(b.x0_total), _zeros(b.z_total), _zeros(b.u_total)
+    b.shift(x0, z, x0n, z_next=zn, u=u, u_next=un, w=_dev(w))
+    zw, itw = _zeros(b.z_total), _zeros(b.n_inst, torch.int32)
+    b.solve_state(x0n, zw, itw, z_init=zn, u_init=un, tol=1e-4, max_iter=10000)
+    torch.cuda.synchronize()
+    itw = itw.cpu().numpy()
+    assert np.all(itw > 0)
+    zh, uh, zwh = z.cpu().numpy(), u.cpu().numpy(), zw.cpu().numpy()
+    rng = np.random.default_rng(6)
+    sample = list(np.argsort(-itw)[:3]) + list(rng.choice(4096, 10, replace=False))
+    for i in sorted(set(int(s) for s in sample)):
+        inst = insts[i]
+        xo = slice(b.x0_off[i], b.x0_off[i] + inst.n)
+        zi = zh[b.z_off[i]:b.z_off[i] + _zsize(inst)].astype(np.float64)
+        ui = _gpu_u_to_oracle(inst, uh[b.u_off[i]:b.u_off[i] + _usize(inst)].astype(np.float64))
+        x0o, zs, us = WS.receding_shift(inst, np.asarray(inst.x0, np.float32).astype(np.float64),
+                                        zi, ui, w=w[xo])
+        g = O.OracleGraph(W.mpc_graph(dataclasses.replace(inst, x0=x0o), box=inst.u_box > 0))
+        g.set_state(zs, us)
+        ko = g.run(20000, tol=1e-4)
+        assert abs(int(itw[i]) - ko) <= max(2, 0.01 * ko), (i, itw[i], ko)
+        zg = zwh[b.z_off[i]:b.z_off[i] + _zsize(inst)]
+        assert rel(zg, g.z) < 1e-3, (i, rel(zg, g.z))
