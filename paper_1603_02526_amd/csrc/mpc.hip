@@ -29,7 +29,8 @@
 
 namespace {
 
-constexpr int WGT = 256;   // threads per workgroup
+constexpr int WGT = 256;   // threads per workgroup (batches with an instance of T > 128)
+constexpr int WGS = 128;   // threads per workgroup when every instance has T <= 128
 constexpr int MN = 12;     // largest state dimension
 constexpr int MM = 4;      // largest input dimension
 constexpr int MK = MN + MM;
@@ -160,7 +161,7 @@ __device__ __forceinline__ void solve_one(const SolveArgs a, int id, int t, int 
   // Stage the parameter block in this instance's LDS slot.
   {
     const float* __restrict__ Pg = a.par + __builtin_amdgcn_readfirstlane(I.par_off);
-    const int nthr = LOCK ? WGT : 64;
+    const int nthr = LOCK ? (int)blockDim.x : 64;
     const int tid = LOCK ? (int)threadIdx.x : (int)(threadIdx.x & 63);
     for (int q = tid; q < o.size; q += nthr) ps[q] = Pg[q];
   }
@@ -468,7 +469,11 @@ __device__ __forceinline__ void solve_dispatch(const SolveArgs a, int id, int t,
   }
 }
 
-__global__ __launch_bounds__(WGT) void mpc_solve_kernel(
+// WG threads per workgroup: WG/64 one-wavefront instances, or one instance
+// of up to WG/64 lockstep wavefronts, per work item.  The register budget
+// is held at two waves per SIMD for both sizes.
+template <int WG>
+__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(2, 2))) void mpc_solve_kernel(
     const MpcInst* __restrict__ inst, const float* __restrict__ par, const float* __restrict__ x0,
     const float* __restrict__ zinit, const float* __restrict__ uinit, float* __restrict__ zout,
     float* __restrict__ uout, int32_t* __restrict__ iters, const int32_t* __restrict__ items,
@@ -488,10 +493,10 @@ __global__ __launch_bounds__(WGT) void mpc_solve_kernel(
   a.tol = tol;
   a.max_iter = max_iter;
   a.rho = rho;
-  __shared__ float xz[TMAX * MN];
-  __shared__ float xm[TMAX * MN];
+  __shared__ float xz[WG * MN];
+  __shared__ float xm[WG * MN];
   __shared__ float red[8];
-  __shared__ __align__(16) float ps[4 * PBLK];   // rows read as 16-byte vectors
+  __shared__ __align__(16) float ps[(WG / 64) * PBLK];   // rows read as 16-byte vectors
   __shared__ int s_item;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   for (;;) {
@@ -710,6 +715,7 @@ struct admm_mpc_batch {
   int32_t* d_counter = nullptr;
   Plan plan;
   int resident = 0;          // workgroups resident per device at full occupancy
+  int wg = WGT;              // threads per workgroup of the persistent launch
   std::vector<int32_t> measured;  // iterations per instance from the last tuning solve
   std::vector<void*> allocs;
   ~admm_mpc_batch() {
@@ -769,11 +775,13 @@ admm_status build_items(admm_mpc_batch* b, const Plan& pl) {
     for (int q = 0; q < 4; ++q) items.push_back(q < (int)pend.size() ? pend[q] : -1);
     pend.clear();
   };
+  // a workgroup holds at most wg/64 one-wavefront instances
+  const int pack = std::min(pl.pack1, b->wg / 64);
   for (int32_t i : ids) {
     const int G = (b->h_inst[i].T + 63) / 64;
     if (G == 1) {
       pend.push_back(i);
-      if ((int)pend.size() == pl.pack1) flush();
+      if ((int)pend.size() == pack) flush();
     } else {
       items.push_back(G);
       items.push_back(i);
@@ -810,7 +818,8 @@ admm_status launch_solve(admm_mpc_batch* b, const float* x0, const float* zinit,
   a.rho = (float)b->rho;
   int grid = b->plan.grid > 0 ? b->plan.grid : b->resident;
   grid = std::max(1, std::min(grid, b->n_items));
-  hipExtLaunchKernelGGL(mpc_solve_kernel, dim3(grid), dim3(WGT), 0, st, e0, e1, 0,
+  hipExtLaunchKernelGGL(b->wg == WGS ? mpc_solve_kernel<WGS> : mpc_solve_kernel<WGT>, dim3(grid),
+                        dim3(b->wg), 0, st, e0, e1, 0,
                         (const MpcInst*)a.inst, a.par, a.x0, a.zinit, a.uinit, a.zout, a.uout,
                         a.iters, a.items, a.n_items, a.counter, a.tol, a.max_iter, a.rho);
   ADMM_HIP(hipGetLastError());
@@ -925,7 +934,13 @@ admm_status admm_mpc_batch_create(int32_t n_inst, const int32_t* T, const int32_
   ADMM_HIP(hipMemcpy(b->d_inst, b->h_inst.data(), sizeof(MpcInst) * n_inst, hipMemcpyHostToDevice));
   ADMM_HIP(hipMemcpy(b->d_par, par.data(), sizeof(float) * par.size(), hipMemcpyHostToDevice));
   int per_cu = 0, cus = 0;
-  ADMM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, mpc_solve_kernel, WGT, 0));
+  int maxT = 0;
+  for (int32_t i = 0; i < n_inst; ++i) maxT = std::max(maxT, (int)T[i]);
+  b->wg = maxT <= WGS ? WGS : WGT;
+  if (b->wg == WGS)
+    ADMM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, mpc_solve_kernel<WGS>, WGS, 0));
+  else
+    ADMM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, mpc_solve_kernel<WGT>, WGT, 0));
   ADMM_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device));
   b->resident = std::max(1, per_cu) * std::max(1, cus);
   if ((s = build_items(b.get(), Plan()))) return s;

@@ -143,3 +143,54 @@ class WarmStart:
             best = min(best, time.perf_counter() - t0)
         it = self.iters.cpu().numpy().copy()
         return best, it
+
+
+class Family:
+    """Several trained systems solved as one batch: every system's
+    instances in one persistent launch (a batch finishes with its slowest
+    instance, so one launch over all systems overlaps their tails).  Each
+    system's network writes its block of the initial trajectories; the
+    dual completion and the solve run once for the whole batch."""
+
+    def __init__(self, starts, device: int = 0):
+        import torch
+        self.torch = torch
+        self.starts = list(starts)
+        insts = []
+        for ws in self.starts:
+            insts += [_Inst(ws.sys)] * ws.batch
+        self.solver = MPCm.MPCBatch(insts, rho=1.0, device=device)
+        dev = torch.device("cuda", device)
+        self.z = torch.zeros(self.solver.z_total, dtype=torch.float32, device=dev)
+        self.z0 = torch.zeros(self.solver.z_total, dtype=torch.float32, device=dev)
+        self.iters = torch.zeros(self.solver.n_inst, dtype=torch.int32, device=dev)
+        self.blocks = []
+        off = 0
+        for ws in self.starts:
+            n = ws.batch * ws.sys.z_dim
+            self.blocks.append((off, n))
+            off += n
+
+    def solve(self, x0s, x0_all, mode: str, tol: float = 1e-4, max_iter: int = 20000):
+        """x0s: per system device [batch, n]; x0_all: their concatenation
+        (flat).  Modes as WarmStart.solve."""
+        if mode == "cold":
+            self.solver.solve(x0_all, self.z, self.iters, tol=tol, max_iter=max_iter)
+        else:
+            for ws, x0, (off, n) in zip(self.starts, x0s, self.blocks):
+                ws.net.forward(x0, self.z0[off:off + n].view(ws.batch, -1))
+            self.solver.solve(x0_all, self.z, self.iters, z_init=self.z0,
+                              dual=(mode == "warm"), tol=tol, max_iter=max_iter)
+        return self.z, self.iters
+
+    def timed(self, x0s, x0_all, mode: str, reps: int = 3, tol: float = 1e-4):
+        torch = self.torch
+        best = 1e30
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            self.solve(x0s, x0_all, mode, tol=tol)
+            torch.cuda.synchronize()
+            best = min(best, time.perf_counter() - t0)
+        return best, self.iters.cpu().numpy().copy()
+

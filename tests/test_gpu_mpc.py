@@ -220,3 +220,33 @@ def test_full_batch_4096_sampled_against_oracle():
         cg = O.mpc_objective(inst, zsplit[i])["cost"]
         assert abs(cg - co) <= 1e-3 * abs(co), (i, cg, co)
         assert rel(zsplit[i], zo) < 1e-3, (i, rel(zsplit[i], zo))
+
+
+def test_short_horizon_batch_on_128_thread_workgroups():
+    """A batch whose instances all have T <= 128 runs on 128-thread
+    workgroups (twice as many resident).  Its results equal, bit for bit,
+    those of the same instances in a batch that also holds a T = 200
+    instance (256-thread workgroups), under every packing, and match the
+    oracle after 50 iterations."""
+    M = _mpc()
+    short = W.mpc_batch(40, seed=67, T_range=(20, 128))
+    rng = np.random.default_rng(68)
+    A_, B_ = W.mpc_system(rng, 6, 2)
+    long_ = W.MPCInstance(200, 6, 2, A_, B_, rng.standard_normal(6), np.ones(6),
+                          np.full(2, 0.1), 1.0)
+    a = M.MPCBatch(short)
+    b = M.MPCBatch(short + [long_])
+    assert a.plan()["resident"] > b.plan()["resident"]
+    za, ia = _solve(a, short, tol=1e-4, max_iter=10000)
+    zb, ib = _solve(b, short + [long_], tol=1e-4, max_iter=10000)
+    assert np.array_equal(ia, ib[:-1])
+    assert np.array_equal(za, zb[:a.z_total])
+    for pack in (4, 2, 1):
+        a.set_plan(pack, 1, 0)
+        z2, i2 = _solve(a, short, tol=1e-4, max_iter=10000)
+        assert np.array_equal(z2, za) and np.array_equal(i2, ia)
+    z50, _ = _solve(a, short, tol=1e-30, max_iter=50)
+    for i in range(0, 40, 5):
+        zo, _ = _oracle(short[i], 50)
+        zi = z50[a.z_off[i]:a.z_off[i] + short[i].T * (short[i].n + short[i].m)]
+        assert rel(zi, zo) < 1e-4, (i, rel(zi, zo))
