@@ -288,7 +288,8 @@ admm_status admm_mpc_batch_shift(admm_mpc_batch* b, const float* x0, const float
                                  float* u_next, void* stream);
 
 /* Schedule of the persistent launch: pack1 = instances per workgroup for
- * T <= 64 (1, 2 or 4), order (0 as given, 1 most work per iteration first,
+ * T <= 64 (1, 2 or 4; at most 2 in a batch whose instances all have
+ * T <= 128, which runs on 128-thread workgroups), order (0 as given, 1 most work per iteration first,
  * 2 grouped by (n, m), 3 longest expected solve first: the iteration counts
  * of the autotuner's cold solve times the latency of one iteration; as 1
  * before a tuning run), grid = workgroups (0: as many as fit on the device
