@@ -105,7 +105,13 @@ def _iter_stats(it):
 
 def bench_mpc_batch(torch):
     """4096 uneven instances (T 20..200, n 4..12, m 2..4), cold start, to
-    residual 1e-4, one persistent launch with the autotuned schedule."""
+    residual 1e-4, one persistent launch.  The reported schedule is the
+    autotuner's fastest among the plans that do not depend on the
+    instances' data (instances per workgroup, order by work or by shape,
+    grid).  ``measured_order`` times the plan that starts the instances
+    with the most iterations in the tuner's own cold solve first: that
+    knowledge comes from solving these same instances, as a controller
+    that solves the same instances every cycle would have it."""
     import numpy as np
     import workloads as W
     from paper_1603_02526_amd import mpc as M
@@ -115,19 +121,34 @@ def bench_mpc_batch(torch):
     z = torch.zeros(b.z_total, device="cuda")
     it = torch.zeros(b.n_inst, dtype=torch.int32, device="cuda")
     cand = b.tune(x0, z, it, tol=1e-4, reps=2)
-    b.solve(x0, z, it, tol=1e-4)
-    torch.cuda.synchronize()
-    best = 1e30
-    for _ in range(5):
-        t0 = time.perf_counter()
+    # candidate k: pack (4, 2, 1)[k // 6], order (1, 2, 3)[(k // 2) % 3],
+    # grid resident set (k even) or one workgroup per item (k odd)
+    plans = [(p, o, g) for p in (4, 2, 1) for o in (1, 2, 3) for g in (0, 1)]
+
+    def timed(plan):
+        p, o, g = plan
+        b.set_plan(p, o, 0 if g == 0 else b.n_inst)
         b.solve(x0, z, it, tol=1e-4)
         torch.cuda.synchronize()
-        best = min(best, time.perf_counter() - t0)
+        best = 1e30
+        for _ in range(5):
+            t0 = time.perf_counter()
+            b.solve(x0, z, it, tol=1e-4)
+            torch.cuda.synchronize()
+            best = min(best, time.perf_counter() - t0)
+        return best
+
+    k3 = min((k for k in range(len(plans)) if plans[k][1] == 3), key=lambda k: cand[k])
+    t3 = timed(plans[k3])
+    k = min((k for k in range(len(plans)) if plans[k][1] != 3), key=lambda k: cand[k])
+    best = timed(plans[k])
     its = it.cpu().numpy()
     return dict(instances=4096, seconds_per_batch=best, solves_per_s=4096 / best,
                 iterations=_iter_stats(its), plan=b.plan(),
                 tuner_candidates_ms=[round(c, 3) for c in cand],
-                instance_iterations_per_s=float(np.abs(its).sum()) / best)
+                instance_iterations_per_s=float(np.abs(its).sum()) / best,
+                measured_order=dict(seconds_per_batch=t3, solves_per_s=4096 / t3,
+                                    plan=dict(zip(("pack1", "order", "grid"), plans[k3]))))
 
 
 def bench_mpc_closed_loop(torch, cycles=8, sd=0.1):
