@@ -261,8 +261,8 @@ __device__ __forceinline__ void solve_one(const SolveArgs a, int id, int t, int 
   for (int it = 1; it <= a.max_iter; ++it) {
     float ax[N], au[MM], bv[N], xqu[MM], xbx[MM], xqx[N];
     float rloc = 0.f, sloc = 0.f;
-    // The parameter block is re-read every iteration from the scalar cache:
-    // an opaque zero offset keeps the compiler from hoisting several hundred
+    // The parameter block is re-read from LDS every iteration: an opaque
+    // zero offset keeps the compiler from hoisting several hundred
     // loop-invariant matrix entries into registers.
     int zoff;
     asm volatile("s_mov_b32 %0, 0" : "=s"(zoff));
