@@ -20,6 +20,11 @@ Also printed on the same JSON line:
                 reported under secondary for the pure-HBM comparison;
   cpu_baseline  the FP64 oracle on this host's CPU, one core, on a bounded
                 sample (100 iterations of the same graph by default);
+  cpu_multicore the same oracle source built with OpenMP (one parallel
+                loop per update, the paper's first CPU scheme) on up to 16
+                threads, same sample; cpu_host names the CPU; speedups sets
+                the GPU / serial and GPU / multi-core ratios beside the
+                paper's (on its own hardware);
   secondary     the other workloads measured the same way (10-disk
                 triangle, 100k-point SVM).
 """
@@ -82,13 +87,30 @@ def time_solve(g, iters, steps, warmup, torch, stream):
     return (time.perf_counter() - t0) / steps
 
 
-def cpu_baseline(problem, iters):
+def cpu_baseline(problem, iters, openmp=False):
+    """The FP64 oracle on the host: serial, or its OpenMP build (threads from
+    OMP_NUM_THREADS, else up to 16).  Returns (edge-updates/s, seconds,
+    threads)."""
+    if openmp:
+        os.environ.setdefault("OMP_NUM_THREADS", str(min(16, os.cpu_count() or 1)))
     import oracle
-    o = oracle.OracleGraph(problem)
+    o = oracle.OracleGraph(problem, openmp=openmp)
+    threads = int(o._L.orc_threads())
     t0 = time.perf_counter()
     o.run(iters)
     dt = time.perf_counter() - t0
-    return problem.n_edges * iters / dt, dt
+    return problem.n_edges * iters / dt, dt, threads
+
+
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def _iter_stats(it):
@@ -418,10 +440,22 @@ def main():
 
     if not args.no_cpu:
         cb_iters = args.cpu_iters
-        v, dt = cpu_baseline(prob, cb_iters)
+        v, dt, _ = cpu_baseline(prob, cb_iters)
         out["cpu_baseline"] = dict(value=v, unit="edge-updates/s", cores=1, kind="oracle",
                                    sample=f"{name}: {cb_iters} iterations of the full graph "
                                           f"({dt:.1f} s, serial FP64)")
+        vm, dtm, thr = cpu_baseline(prob, cb_iters, openmp=True)
+        out["cpu_multicore"] = dict(
+            value=vm, unit="edge-updates/s", cores=thr,
+            kind="oracle, OpenMP build (one parallel loop per update, bit-identical results)",
+            sample=f"{name}: {cb_iters} iterations of the full graph ({dtm:.1f} s, FP64)")
+        out["cpu_host"] = dict(model=_cpu_model(), logical_cpus=os.cpu_count())
+        out["speedups"] = dict(
+            gpu_over_serial=out["value"] / v, gpu_over_multicore=out["value"] / vm,
+            multicore_over_serial=vm / v,
+            paper=dict(gpu_over_serial="10-18x", multicore_over_serial="5-9x",
+                       hardware="NVIDIA Tesla K40 against one core of an AMD Opteron 6300 "
+                                "(Abu Dhabi, 2.8 GHz); multi-core runs on up to 32 of its cores"))
     print(json.dumps(out))
 
 

@@ -27,26 +27,33 @@ KIND = dict(nonoverlap=1, wall=2, radius=3, quad=4, box=5, hinge=6, l2=7,
             lindyn=8, lindyn0=9, minerr=10, equal=11, margin=12)
 
 
+LIB_OMP_PATH = os.path.join(HERE, "liboracle_omp.so")
+
+
 def build(force: bool = False) -> str:
-    """Compile the oracle with g++ (serial, -O2, no fast-math)."""
-    if force or not os.path.exists(LIB_PATH) or \
-            os.path.getmtime(LIB_PATH) < os.path.getmtime(SRC):
-        tmp = LIB_PATH + f".tmp{os.getpid()}"
-        subprocess.check_call(["g++", "-O2", "-std=c++17", "-fPIC", "-shared",
-                               "-fno-fast-math", "-ffp-contract=off",
-                               SRC, "-o", tmp])
-        os.replace(tmp, LIB_PATH)
+    """Compile the oracle with g++ (-O2, no fast-math): the serial library
+    and the same source with OpenMP (multi-core timing; identical results)."""
+    for path, extra in ((LIB_PATH, []), (LIB_OMP_PATH, ["-fopenmp"])):
+        if force or not os.path.exists(path) or \
+                os.path.getmtime(path) < os.path.getmtime(SRC):
+            tmp = path + f".tmp{os.getpid()}"
+            subprocess.check_call(["g++", "-O2", "-std=c++17", "-fPIC", "-shared",
+                                   "-fno-fast-math", "-ffp-contract=off", *extra,
+                                   SRC, "-o", tmp])
+            os.replace(tmp, path)
     return LIB_PATH
 
 
-_lib = None
+_libs = {}
 
 
-def lib():
-    global _lib
-    if _lib is None:
+def lib(openmp: bool = False):
+    """The serial oracle library, or its OpenMP build (threads from
+    OMP_NUM_THREADS)."""
+    L = _libs.get(openmp)
+    if L is None:
         build()
-        L = ctypes.CDLL(LIB_PATH)
+        L = ctypes.CDLL(LIB_OMP_PATH if openmp else LIB_PATH)
         vp, ip, dp, lp = (ctypes.c_void_p, ctypes.POINTER(ctypes.c_int),
                           ctypes.POINTER(ctypes.c_double),
                           ctypes.POINTER(ctypes.c_long))
@@ -72,8 +79,9 @@ def lib():
         L.orc_prox.restype = ctypes.c_int
         L.orc_prox.argtypes = [ctypes.c_int, ctypes.c_int, ip, dp,
                                ctypes.c_int, ctypes.c_double, dp, dp]
-        _lib = L
-    return _lib
+        L.orc_threads.restype = ctypes.c_int
+        _libs[openmp] = L
+    return L
 
 
 def _ip(a):
@@ -101,8 +109,8 @@ class OracleGraph:
     """Algorithm 2 in FP64 on a ``workloads.Problem``."""
 
     def __init__(self, problem, rho: Optional[float] = None,
-                 alpha: Optional[float] = None):
-        L = lib()
+                 alpha: Optional[float] = None, openmp: bool = False):
+        L = self._L = lib(openmp)
         dims = np.ascontiguousarray(problem.var_dims, dtype=np.int32)
         self._h = L.orc_graph_create(len(dims), _ip(dims))
         for g in problem.groups:
@@ -122,8 +130,8 @@ class OracleGraph:
         self.set_state(problem.z0)
 
     def __del__(self):
-        if getattr(self, "_h", None) and _lib is not None:
-            _lib.orc_graph_destroy(self._h)
+        if getattr(self, "_h", None) and getattr(self, "_L", None) is not None:
+            self._L.orc_graph_destroy(self._h)
             self._h = None
 
     def set_state(self, z, u=None):
@@ -132,12 +140,12 @@ class OracleGraph:
         if u is not None:
             u = np.ascontiguousarray(u, dtype=np.float64)
             assert u.shape == (self.n_slots,)
-            lib().orc_set_state(self._h, _dp(z), _dp(u))
+            self._L.orc_set_state(self._h, _dp(z), _dp(u))
         else:
-            lib().orc_set_state(self._h, _dp(z), None)
+            self._L.orc_set_state(self._h, _dp(z), None)
 
     def run(self, iters: int, tol: float = 0.0) -> int:
-        return int(lib().orc_run(self._h, int(iters), float(tol)))
+        return int(self._L.orc_run(self._h, int(iters), float(tol)))
 
     def _get(self, fn, n):
         out = np.zeros(n)
@@ -146,30 +154,30 @@ class OracleGraph:
 
     @property
     def z(self) -> np.ndarray:
-        return self._get(lib().orc_get_z, self.n_z)
+        return self._get(self._L.orc_get_z, self.n_z)
 
     @property
     def u(self) -> np.ndarray:
-        return self._get(lib().orc_get_u, self.n_slots)
+        return self._get(self._L.orc_get_u, self.n_slots)
 
     @property
     def x(self) -> np.ndarray:
-        return self._get(lib().orc_get_x, self.n_slots)
+        return self._get(self._L.orc_get_x, self.n_slots)
 
     @property
     def m(self) -> np.ndarray:
-        return self._get(lib().orc_get_m, self.n_slots)
+        return self._get(self._L.orc_get_m, self.n_slots)
 
     @property
     def slot_z(self) -> np.ndarray:
         out = np.zeros(self.n_slots, dtype=np.int64)
-        lib().orc_get_slot_z(self._h,
+        self._L.orc_get_slot_z(self._h,
                              out.ctypes.data_as(ctypes.POINTER(ctypes.c_long)))
         return out
 
     def residuals(self) -> Tuple[float, float]:
         r, s = ctypes.c_double(), ctypes.c_double()
-        lib().orc_residuals(self._h, ctypes.byref(r), ctypes.byref(s))
+        self._L.orc_residuals(self._h, ctypes.byref(r), ctypes.byref(s))
         return r.value, s.value
 
 

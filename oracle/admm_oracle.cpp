@@ -15,8 +15,14 @@
 //     u-update: u_e = u_e + alpha (x_e - z_b)
 //     n-update: n_e = z_b - u_e
 // Each update is its own loop over factors, edges or variables, in the
-// paper's order, summing in edge-creation order.  rho and alpha are one
-// value for all edges.
+// paper's order; the z-update sums each variable's incoming m in
+// edge-creation order.  rho and alpha are one value for all edges.
+//
+// The same source builds serially (the default) or with OpenMP for a
+// multi-core timing: each of the loops is then a parallel loop over its own
+// index (the paper's first CPU scheme, one parallel loop per update).
+// Every element is still computed by the same arithmetic in the same order,
+// so both builds give bit-identical results.
 //
 // Proximal operators (paper appendix, with the readings listed in the
 // design notes):
@@ -52,6 +58,10 @@
 #include <cstring>
 #include <vector>
 
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
 namespace {
 
 enum Kind {
@@ -85,6 +95,8 @@ struct Graph {
   long nslot = 0;            // total edge slots
   std::vector<long> slot_z;  // z index of each edge slot
   std::vector<double> z, zprev, x, m, u, n;
+  std::vector<long> zbeg, zedges;  // edges of each variable, in creation order
+  long lists_for = -1;             // nslot the lists were built for
   double rho = 1.0, alpha = 1.0;
   double r_primal = 0.0, r_dual = 0.0;
 };
@@ -372,37 +384,64 @@ int prox_apply(int kind, int arity, const int* dims, const double* p, int plen,
   }
 }
 
+// The edges of every variable in creation order (the order in which the
+// z-update adds them).
+void build_lists(Graph& g) {
+  g.zbeg.assign(g.nz + 1, 0);
+  for (long e = 0; e < g.nslot; ++e) g.zbeg[g.slot_z[e] + 1]++;
+  for (long b = 0; b < g.nz; ++b) g.zbeg[b + 1] += g.zbeg[b];
+  g.zedges.resize(g.nslot);
+  std::vector<long> next(g.zbeg.begin(), g.zbeg.end() - 1);
+  for (long e = 0; e < g.nslot; ++e) g.zedges[next[g.slot_z[e]]++] = e;
+  g.lists_for = g.nslot;
+}
+
 // One iteration of Algorithm 2, each update its own loop.
 void iterate(Graph& g) {
   const long S = g.nslot;
+  const long NF = static_cast<long>(g.F.size());
+  if (g.lists_for != S) build_lists(g);
   // n-update of the previous iteration (n = z - u), kept explicit.
+#pragma omp parallel for schedule(static)
   for (long e = 0; e < S; ++e) g.n[e] = g.z[g.slot_z[e]] - g.u[e];
   // x-update.
-  std::vector<int> dims;
-  for (const Factor& f : g.F) {
-    dims.resize(f.vars.size());
-    for (size_t k = 0; k < f.vars.size(); ++k) dims[k] = g.dim[f.vars[k]];
-    const long s0 = f.slot[0];
-    prox_apply(f.kind, static_cast<int>(f.vars.size()), dims.data(),
-               f.p.data(), static_cast<int>(f.p.size()), g.rho,
-               &g.n[s0], &g.x[s0]);
+#pragma omp parallel
+  {
+    std::vector<int> dims;
+#pragma omp for schedule(dynamic, 256)
+    for (long i = 0; i < NF; ++i) {
+      const Factor& f = g.F[i];
+      dims.resize(f.vars.size());
+      for (size_t k = 0; k < f.vars.size(); ++k) dims[k] = g.dim[f.vars[k]];
+      const long s0 = f.slot[0];
+      prox_apply(f.kind, static_cast<int>(f.vars.size()), dims.data(),
+                 f.p.data(), static_cast<int>(f.p.size()), g.rho,
+                 &g.n[s0], &g.x[s0]);
+    }
   }
   // m-update.
+#pragma omp parallel for schedule(static)
   for (long e = 0; e < S; ++e) g.m[e] = g.x[e] + g.u[e];
-  // z-update: sum in edge-creation order; a variable with no edge keeps z.
+  // z-update: each variable's incoming m summed in edge-creation order; a
+  // variable with no edge keeps z.
   g.zprev = g.z;
-  std::vector<double> num(g.nz, 0.0), den(g.nz, 0.0);
-  for (long e = 0; e < S; ++e) {
-    num[g.slot_z[e]] += g.rho * g.m[e];
-    den[g.slot_z[e]] += g.rho;
+#pragma omp parallel for schedule(static)
+  for (long b = 0; b < g.nz; ++b) {
+    double num = 0.0, den = 0.0;
+    for (long q = g.zbeg[b]; q < g.zbeg[b + 1]; ++q) {
+      num += g.rho * g.m[g.zedges[q]];
+      den += g.rho;
+    }
+    if (den > 0.0) g.z[b] = num / den;
   }
-  for (long b = 0; b < g.nz; ++b)
-    if (den[b] > 0.0) g.z[b] = num[b] / den[b];
   // u-update.
+#pragma omp parallel for schedule(static)
   for (long e = 0; e < S; ++e) g.u[e] += g.alpha * (g.x[e] - g.z[g.slot_z[e]]);
-  // Stopping measures.
+  // Stopping measures (maxima: the same in any order).
   double r = 0.0, s = 0.0;
+#pragma omp parallel for schedule(static) reduction(max : r)
   for (long e = 0; e < S; ++e) r = std::max(r, std::fabs(g.x[e] - g.z[g.slot_z[e]]));
+#pragma omp parallel for schedule(static) reduction(max : s)
   for (long b = 0; b < g.nz; ++b) s = std::max(s, std::fabs(g.z[b] - g.zprev[b]));
   g.r_primal = r;
   g.r_dual = g.rho * s;
@@ -411,6 +450,15 @@ void iterate(Graph& g) {
 }  // namespace
 
 extern "C" {
+
+// Threads the loops run on (1 in the serial build).
+int orc_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
 
 void* orc_graph_create(int n_vars, const int* dims) {
   Graph* g = new Graph();
