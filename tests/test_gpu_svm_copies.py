@@ -21,7 +21,7 @@ pytestmark = pytest.mark.gpu
 FP32, FP64 = A.FP32, A.FP64
 
 
-@pytest.mark.parametrize("N,d", [(300, 5), (257, 20), (2, 3)])
+@pytest.mark.parametrize("N,d", [(300, 5), (257, 20), (130, 40), (2, 3)])
 @pytest.mark.parametrize("prec,iters,tol", [(FP64, 60, 1e-9), (FP32, 50, 1e-4)])
 def test_copies_parity(N, d, prec, iters, tol):
     p = W.svm_copies(N, d, seed=91 + N)
