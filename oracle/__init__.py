@@ -80,6 +80,9 @@ def lib(openmp: bool = False):
         L.orc_prox.argtypes = [ctypes.c_int, ctypes.c_int, ip, dp,
                                ctypes.c_int, ctypes.c_double, dp, dp]
         L.orc_threads.restype = ctypes.c_int
+        L.orc_set_factor_weights.restype = ctypes.c_int
+        L.orc_set_factor_weights.argtypes = [vp, ctypes.c_long, ctypes.c_long,
+                                             ctypes.c_double, ctypes.c_double]
         _libs[openmp] = L
     return L
 
@@ -113,6 +116,7 @@ class OracleGraph:
         L = self._L = lib(openmp)
         dims = np.ascontiguousarray(problem.var_dims, dtype=np.int32)
         self._h = L.orc_graph_create(len(dims), _ip(dims))
+        first = 0
         for g in problem.groups:
             vid = np.ascontiguousarray(g.var_ids, dtype=np.int32)
             par = np.ascontiguousarray(g.params, dtype=np.float64)
@@ -123,6 +127,11 @@ class OracleGraph:
                                    1 if g.shared else 0)
             if rc != 0:
                 raise ValueError("oracle: bad factor group")
+            grho, galpha = getattr(g, "rho", None), getattr(g, "alpha", None)
+            if grho is not None or galpha is not None:
+                L.orc_set_factor_weights(self._h, first, g.n, float(grho or 0.0),
+                                         float(galpha or 0.0))
+            first += g.n
         L.orc_set_params(self._h, float(problem.rho if rho is None else rho),
                          float(problem.alpha if alpha is None else alpha))
         self.n_slots = int(L.orc_num_slots(self._h))

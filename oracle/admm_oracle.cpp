@@ -15,8 +15,11 @@
 //     u-update: u_e = u_e + alpha (x_e - z_b)
 //     n-update: n_e = z_b - u_e
 // Each update is its own loop over factors, edges or variables, in the
-// paper's order; the z-update sums each variable's incoming m in
-// edge-creation order.  rho and alpha are one value for all edges.
+// paper's order; the z-update sums each variable's incoming rho m in
+// edge-creation order.  Every edge carries its own rho_(a,b) and
+// alpha_(a,b) (Algorithm 2); here they are set per group of factors (all
+// edges of one factor share them, as the appendix's closed forms assume),
+// and default to one graph-wide value.
 //
 // The same source builds serially (the default) or with OpenMP for a
 // multi-core timing: each of the loops is then a parallel loop over its own
@@ -85,6 +88,7 @@ struct Factor {
   std::vector<long> slot;    // first slot of each edge in the edge arrays
   int nslots;                // total scalar slots of this factor
   std::vector<double> p;     // parameters
+  double rho = 0.0, alpha = 0.0;  // this factor's edge weights (0: the graph's)
 };
 
 struct Graph {
@@ -96,7 +100,8 @@ struct Graph {
   std::vector<long> slot_z;  // z index of each edge slot
   std::vector<double> z, zprev, x, m, u, n;
   std::vector<long> zbeg, zedges;  // edges of each variable, in creation order
-  long lists_for = -1;             // nslot the lists were built for
+  std::vector<double> erho, ealpha, vrho;  // per edge slot rho, alpha; per z the largest rho
+  long lists_for = -1;             // nslot the tables were built for
   double rho = 1.0, alpha = 1.0;
   double r_primal = 0.0, r_dual = 0.0;
 };
@@ -385,8 +390,17 @@ int prox_apply(int kind, int arity, const int* dims, const double* p, int plen,
 }
 
 // The edges of every variable in creation order (the order in which the
-// z-update adds them).
+// z-update adds them), and every edge slot's rho and alpha.
 void build_lists(Graph& g) {
+  g.erho.assign(g.nslot, g.rho);
+  g.ealpha.assign(g.nslot, g.alpha);
+  for (const Factor& f : g.F)
+    for (long e = f.slot[0]; e < f.slot[0] + f.nslots; ++e) {
+      if (f.rho > 0.0) g.erho[e] = f.rho;
+      if (f.alpha > 0.0) g.ealpha[e] = f.alpha;
+    }
+  g.vrho.assign(g.nz, 0.0);
+  for (long e = 0; e < g.nslot; ++e) g.vrho[g.slot_z[e]] = std::max(g.vrho[g.slot_z[e]], g.erho[e]);
   g.zbeg.assign(g.nz + 1, 0);
   for (long e = 0; e < g.nslot; ++e) g.zbeg[g.slot_z[e] + 1]++;
   for (long b = 0; b < g.nz; ++b) g.zbeg[b + 1] += g.zbeg[b];
@@ -415,7 +429,7 @@ void iterate(Graph& g) {
       for (size_t k = 0; k < f.vars.size(); ++k) dims[k] = g.dim[f.vars[k]];
       const long s0 = f.slot[0];
       prox_apply(f.kind, static_cast<int>(f.vars.size()), dims.data(),
-                 f.p.data(), static_cast<int>(f.p.size()), g.rho,
+                 f.p.data(), static_cast<int>(f.p.size()), f.rho > 0.0 ? f.rho : g.rho,
                  &g.n[s0], &g.x[s0]);
     }
   }
@@ -429,22 +443,24 @@ void iterate(Graph& g) {
   for (long b = 0; b < g.nz; ++b) {
     double num = 0.0, den = 0.0;
     for (long q = g.zbeg[b]; q < g.zbeg[b + 1]; ++q) {
-      num += g.rho * g.m[g.zedges[q]];
-      den += g.rho;
+      const long e = g.zedges[q];
+      num += g.erho[e] * g.m[e];
+      den += g.erho[e];
     }
     if (den > 0.0) g.z[b] = num / den;
   }
   // u-update.
 #pragma omp parallel for schedule(static)
-  for (long e = 0; e < S; ++e) g.u[e] += g.alpha * (g.x[e] - g.z[g.slot_z[e]]);
-  // Stopping measures (maxima: the same in any order).
+  for (long e = 0; e < S; ++e) g.u[e] += g.ealpha[e] * (g.x[e] - g.z[g.slot_z[e]]);
+  // Stopping measures (maxima: the same in any order); the dual residual
+  // weighs each variable's change by the largest rho of its edges.
   double r = 0.0, s = 0.0;
 #pragma omp parallel for schedule(static) reduction(max : r)
   for (long e = 0; e < S; ++e) r = std::max(r, std::fabs(g.x[e] - g.z[g.slot_z[e]]));
 #pragma omp parallel for schedule(static) reduction(max : s)
-  for (long b = 0; b < g.nz; ++b) s = std::max(s, std::fabs(g.z[b] - g.zprev[b]));
+  for (long b = 0; b < g.nz; ++b) s = std::max(s, g.vrho[b] * std::fabs(g.z[b] - g.zprev[b]));
   g.r_primal = r;
-  g.r_dual = g.rho * s;
+  g.r_dual = s;
 }
 
 }  // namespace
@@ -507,10 +523,24 @@ int orc_add_factors(void* h, int kind, int n, int arity, const int* vars,
   return 0;
 }
 
+// rho and alpha of factors [first, first + count) (> 0; 0 restores the
+// graph's value).
+int orc_set_factor_weights(void* h, long first, long count, double rho, double alpha) {
+  Graph* g = static_cast<Graph*>(h);
+  if (first < 0 || count < 0 || first + count > static_cast<long>(g->F.size())) return -1;
+  for (long i = first; i < first + count; ++i) {
+    g->F[i].rho = rho;
+    g->F[i].alpha = alpha;
+  }
+  g->lists_for = -1;
+  return 0;
+}
+
 void orc_set_params(void* h, double rho, double alpha) {
   Graph* g = static_cast<Graph*>(h);
   g->rho = rho;
   g->alpha = alpha;
+  g->lists_for = -1;
 }
 
 long orc_num_slots(void* h) { return static_cast<Graph*>(h)->nslot; }

@@ -40,11 +40,15 @@ class FactorGroup:
 
     var_ids: int32 [n, arity]; params: float64 [n, param_len] or, when
     ``shared`` is true, [param_len] used by every factor of the group.
+    rho, alpha: the edge weights of this group's edges (None: the
+    problem's values).
     """
     kind: str
     var_ids: np.ndarray
     params: np.ndarray
     shared: bool = False
+    rho: Optional[float] = None
+    alpha: Optional[float] = None
 
     @property
     def n(self) -> int:
