@@ -129,10 +129,21 @@ admm_status admm_graph_add_factors(admm_graph* g, int32_t kind,
                                    const double* params, int32_t param_len,
                                    int32_t shared_params);
 
-/* rho (> 0) and alpha (> 0) of every edge (Alg. 2; one value for all
- * edges).  Defaults 1 and 1.  Only before finalize. */
+/* rho (> 0) and alpha (> 0) of the edges (Alg. 2).  Defaults 1 and 1.
+ * alpha is one value for all edges; rho is the value of every edge whose
+ * group has none of its own (below).  Only before finalize. */
 admm_status admm_graph_set_rho(admm_graph* g, double rho);
 admm_status admm_graph_set_alpha(admm_graph* g, double alpha);
+
+/* rho (> 0) of the edges of one group of factors: `group` counts the
+ * admm_graph_add_factors calls from 0.  Algorithm 2 weighs each edge's
+ * prox and its term of the z-average by rho_(a,b); here every edge of the
+ * group gets `rho` (the closed forms assume equal weights within a
+ * factor).  z_b then averages rho_(a,b) m_(a,b) over sum rho_(a,b), and the
+ * dual residual weighs each variable's change by the largest rho of its
+ * edges.  ADMM_E_ARG for a group index out of range or rho <= 0; only
+ * before finalize. */
+admm_status admm_graph_set_group_rho(admm_graph* g, int32_t group, double rho);
 
 /* Layout options, set before finalize.
  *  ADMM_OPT_PAIR_ROWS: disks per row of a dense pair tile (16, 32 or 64;

@@ -79,6 +79,7 @@ def lib():
                                                ctypes.c_int32, ctypes.c_int32])
         _sig(L, "admm_graph_set_rho", st, [VP, ctypes.c_double])
         _sig(L, "admm_graph_set_alpha", st, [VP, ctypes.c_double])
+        _sig(L, "admm_graph_set_group_rho", st, [VP, ctypes.c_int32, ctypes.c_double])
         _sig(L, "admm_graph_finalize", st, [VP, ctypes.c_int32])
         _sig(L, "admm_graph_set_option", st, [VP, ctypes.c_int32, ctypes.c_int64])
         _sig(L, "admm_graph_info_get", st, [VP, ctypes.POINTER(GraphInfo)])
@@ -153,6 +154,10 @@ class Graph:
     def set_rho(self, rho: float):
         check(lib().admm_graph_set_rho(self._h, float(rho)))
 
+    def set_group_rho(self, group: int, rho: float):
+        """rho of the edges of the group-th add_factors call."""
+        check(lib().admm_graph_set_group_rho(self._h, int(group), float(rho)))
+
     def set_alpha(self, alpha: float):
         check(lib().admm_graph_set_alpha(self._h, float(alpha)))
 
@@ -219,8 +224,13 @@ class Graph:
         """Build from an object with var_dims, groups (kind, var_ids, params,
         shared), rho, alpha and z0.  device=None skips finalize."""
         g = cls(problem.var_dims, precision)
-        for grp in problem.groups:
+        for i, grp in enumerate(problem.groups):
             g.add_factors(grp.kind, grp.var_ids, grp.params, grp.shared)
+            if getattr(grp, "rho", None) is not None:
+                g.set_group_rho(i, grp.rho)
+            if getattr(grp, "alpha", None) is not None:
+                raise ValueError("the library takes one alpha for all edges; "
+                                 "per-group alpha is not supported")
         g.set_rho(problem.rho if rho is None else rho)
         g.set_alpha(problem.alpha if alpha is None else alpha)
         if pair_rows:

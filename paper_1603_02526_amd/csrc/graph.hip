@@ -36,6 +36,7 @@ namespace {
 struct Group {
   int32_t kind, n, arity, plen;
   bool shared;
+  double rho = 0.0;            // rho of this group's edges (0: the graph's)
   std::vector<int32_t> vids;   // [n * arity]
   std::vector<double> params;  // [n * plen] or [plen]
   const double* prm(int64_t f) const {
@@ -54,7 +55,10 @@ struct Plan {
   int64_t w_base = 0, l_base = 0;  // medium / short z lists: first pool position
   std::vector<int32_t> var_b, var_w, var_l;   // z lists: long, medium, short
   std::vector<int64_t> rng_b, rng_w;
-  std::vector<double> deg_b, deg_w, deg_l;
+  std::vector<double> deg_b, deg_w, deg_l;  // per z list: sum of its edges' rho / graph rho
+  bool weighted = false;        // groups with different rho: weighted z-sums
+  std::vector<double> wz;       // weighted: relative rho of every contribution position
+  std::vector<double> rmz;      // weighted: per z scalar, the largest rho of its edges
   std::vector<int64_t> upos;    // user slot -> pool position of m
   std::vector<int32_t> uz;      // user slot -> z index
   int64_t xblocks = 0;
@@ -274,20 +278,28 @@ admm_status build_plan(admm_graph& g, Plan& P, bool no_tiles) {
   // index-buffer slot that will receive its position in the z-major buffer.
   struct Emit { int64_t z; int64_t key; };
   std::vector<Emit> em;
-  std::vector<int64_t> deg(g.nz, 0);
+  std::vector<double> deg(g.nz, 0.0);   // sum of relative rho over each scalar's edges
+  std::vector<double> rmz(g.nz, 0.0);
+  struct EmRange { size_t end; double rho; };
+  std::vector<EmRange> em_rho;
   P.upos.assign(g.n_slots, 0);
   P.uz.assign(g.n_slots, 0);
   int64_t us = 0;      // running user slot
   int64_t blocks = 0;
   for (const Group& gr : g.groups) {
+    const double rg = gr.rho > 0.0 ? gr.rho : g.rho;
+    // z-sum weight relative to the graph's rho: exactly 1 for every edge of a
+    // graph without group weights, so such graphs keep their unweighted sums
+    const double rw = rg / g.rho;
+    if (rg != g.rho) P.weighted = true;
     std::string why;
     int32_t nn = 0, mm = 0;
     if (!kind_dim_ok(g, gr, why, nn, mm)) return admmi::set_err(ADMM_E_ARG, "%s", why.c_str());
     if (gr.kind == KD_RADIUS)
       for (int64_t f = 0; f < gr.n; ++f)
-        if (!(g.rho > gr.prm(f)[0]))
+        if (!(rg > gr.prm(f)[0]))
           return admmi::set_err(ADMM_E_NUMERIC, "RADIUS factor needs rho > gamma (rho=%g, gamma=%g)",
-                                g.rho, gr.prm(f)[0]);
+                                rg, gr.prm(f)[0]);
     if (gr.n == 0) continue;
     BucketDesc b{};
     b.kind = gr.kind;
@@ -384,7 +396,7 @@ admm_status build_plan(admm_graph& g, Plan& P, bool no_tiles) {
         for (int s = 0; s < 6; ++s) {
           P.upos[us] = base + (int64_t)s * RB * CB;
           P.uz[us] = (int32_t)zs[s];
-          deg[zs[s]]++;
+          deg[zs[s]] += rw; rmz[zs[s]] = std::max(rmz[zs[s]], rg);
           ++us;
         }
       }
@@ -409,7 +421,7 @@ admm_status build_plan(admm_graph& g, Plan& P, bool no_tiles) {
         for (int k = 0; k < d; ++k) { par[k * b.nfp + f] = y * p[k]; aa += p[k] * p[k]; }
         par[d * b.nfp + f] = y;
         par[(d + 1) * b.nfp + f] = C;
-        par[(d + 2) * b.nfp + f] = g.rho / (aa + 1.0);
+        par[(d + 2) * b.nfp + f] = rg / (aa + 1.0);
       }
       P.n_m += (int64_t)gr.arity * b.nfp;
       const int64_t tiles = (gr.n + NT - 1) / NT;
@@ -424,7 +436,7 @@ admm_status build_plan(admm_graph& g, Plan& P, bool no_tiles) {
         for (int e = 0; e < gr.arity; ++e) {
           P.upos[us] = b.m_off + (int64_t)e * b.nfp + f;
           P.uz[us] = (int32_t)zof(f, e);
-          deg[zof(f, e)]++;
+          deg[zof(f, e)] += rw; rmz[zof(f, e)] = std::max(rmz[zof(f, e)], rg);
           ++us;
         }
       P.algo_elems += (int64_t)gr.n * (2 * gr.arity + d + 3);
@@ -451,7 +463,7 @@ admm_status build_plan(admm_graph& g, Plan& P, bool no_tiles) {
             P.idx[i0 + e * b.nfp + j + c] = (int32_t)zi;
             P.upos[us] = b.m_off + (int64_t)e * b.nfp + j + c;
             P.uz[us] = (int32_t)zi;
-            deg[zi]++;
+            deg[zi] += rw; rmz[zi] = std::max(rmz[zi], rg);
             ++us;
             em.push_back({zi, b.dst_off + (int64_t)e * b.nfp + j + c});
           }
@@ -486,7 +498,7 @@ admm_status build_plan(admm_graph& g, Plan& P, bool no_tiles) {
         for (int k = 0; k < d; ++k) { par[k * b.nfp + f] = y * p[k]; xx += p[k] * p[k]; }
         par[d * b.nfp + f] = y;
         par[(d + 1) * b.nfp + f] = INFINITY;
-        par[(d + 2) * b.nfp + f] = g.rho / (xx + 2.0);
+        par[(d + 2) * b.nfp + f] = rg / (xx + 2.0);
       }
       P.n_m += (int64_t)b.nslot * b.nfp;
       b.dst_off = (int64_t)P.idx.size();
@@ -500,7 +512,7 @@ admm_status build_plan(admm_graph& g, Plan& P, bool no_tiles) {
           const int64_t zi = P.idx[i0 + s * b.nfp + f];
           P.upos[us] = b.m_off + (int64_t)s * b.nfp + f;
           P.uz[us] = (int32_t)zi;
-          deg[zi]++;
+          deg[zi] += rw; rmz[zi] = std::max(rmz[zi], rg);
           ++us;
           if (!(b.ub && s == d)) em.push_back({zi, b.dst_off + (int64_t)s * b.nfp + f});
         }
@@ -536,17 +548,17 @@ admm_status build_plan(admm_graph& g, Plan& P, bool no_tiles) {
             P.idx[i0 + s] = (int32_t)zi;
             double p0 = 0.0, p1 = 0.0;
             switch (gr.kind) {
-              case KD_RADIUS: p0 = g.rho / (g.rho - p[0]); break;
-              case KD_QUAD: p0 = g.rho / (g.rho + p[comp]); break;
-              case KD_L2: p0 = g.rho / (g.rho + p[0]); break;
+              case KD_RADIUS: p0 = rg / (rg - p[0]); break;
+              case KD_QUAD: p0 = rg / (rg + p[comp]); break;
+              case KD_L2: p0 = rg / (rg + p[0]); break;
               case KD_BOX: p0 = p[0]; p1 = p[1]; break;
-              case KD_MINERR: p0 = p[0] / g.rho; break;
+              case KD_MINERR: p0 = p[0] / rg; break;
             }
             par[s] = p0;
             par[b.nfp + s] = p1;
             P.upos[us] = b.m_off + s;
             P.uz[us] = (int32_t)zi;
-            deg[zi]++;
+            deg[zi] += rw; rmz[zi] = std::max(rmz[zi], rg);
             ++us;
             em.push_back({zi, b.dst_off + s});
           }
@@ -601,7 +613,7 @@ admm_status build_plan(admm_graph& g, Plan& P, bool no_tiles) {
           for (int k = 0; k < d; ++k) { par[k * b.nfp + f] = p[d] * p[k]; aa += p[k] * p[k]; }
           par[d * b.nfp + f] = p[d];
           par[(d + 1) * b.nfp + f] = p[d + 1];
-          par[(d + 2) * b.nfp + f] = g.rho / (aa + 1.0);
+          par[(d + 2) * b.nfp + f] = rg / (aa + 1.0);
         }
         P.algo_elems += gr.n * (d + 3);
       } else if (lind) {
@@ -663,7 +675,7 @@ admm_status build_plan(admm_graph& g, Plan& P, bool no_tiles) {
             const int64_t pos = b.m_off + (int64_t)s * b.nfp + f;
             P.upos[us] = pos;
             P.uz[us] = (int32_t)zi;
-            deg[zi]++;
+            deg[zi] += rw; rmz[zi] = std::max(rmz[zi], rg);
             ++us;
             em.push_back({zi, b.dst_off + (int64_t)s * b.nfp + f});
           }
@@ -675,7 +687,9 @@ admm_status build_plan(admm_graph& g, Plan& P, bool no_tiles) {
       P.algo_elems += 2 * (int64_t)gr.n * b.nslot;
       P.layout_idx_bytes += (int64_t)gr.n * gr.arity * 4;
     }
+    b.irho = 1.0 / rg;
     P.bt.push_back(b);
+    em_rho.push_back({em.size(), rw});
   }
   if (us != g.n_slots) return admmi::set_err(ADMM_E_ARG, "internal: slot count mismatch");
   if (blocks > 0x7fffffff) return admmi::set_err(ADMM_E_UNSUPPORTED, "graph too large for one launch");
@@ -712,7 +726,7 @@ admm_status build_plan(admm_graph& g, Plan& P, bool no_tiles) {
         P.var_b.push_back((int32_t)zi);
         P.rng_b.push_back(pb);
         P.rng_b.push_back(pb + L);
-        P.deg_b.push_back((double)deg[zi]);
+        P.deg_b.push_back(deg[zi]);
         pb += L;
       } else if (L > LANE_MAX) {
         base[zi] = pad_w ? P.w_base + kw * S_w : pw;
@@ -722,16 +736,29 @@ admm_status build_plan(admm_graph& g, Plan& P, bool no_tiles) {
           P.rng_w.push_back(pw + L);
           pw += L;
         }
-        P.deg_w.push_back((double)deg[zi]);
+        P.deg_w.push_back(deg[zi]);
         ++kw;
       } else {
         base[zi] = P.l_base + kl * LANE_MAX;
         P.var_l.push_back((int32_t)zi);
-        P.deg_l.push_back((double)deg[zi]);
+        P.deg_l.push_back(deg[zi]);
         ++kl;
       }
     }
-    for (auto& e : em) P.idx[e.key] = (int32_t)(base[e.z]++);
+    if (P.weighted) {
+      P.wz.assign(zc_total, 0.0);
+      P.rmz = rmz;
+    }
+    size_t gi = 0;
+    for (size_t q = 0; q < em.size(); ++q) {
+      const Emit& e = em[q];
+      const int64_t pos = base[e.z]++;
+      P.idx[e.key] = (int32_t)pos;
+      if (P.weighted) {
+        while (q >= em_rho[gi].end) ++gi;
+        P.wz[pos] = em_rho[gi].rho;
+      }
+    }
   }
   // pool = [contributions | m regions | x regions], each region aligned
   P.n_m = round_up(P.n_m, 64);
@@ -802,6 +829,8 @@ struct Engine : EngineBase {
   int64_t* upos = nullptr;
   int32_t* uz = nullptr;
   T *bmx = nullptr, *bmz = nullptr;
+  bool weighted = false;           // groups with different rho
+  T *wz = nullptr, *rmz = nullptr;  // weighted: rho per contribution position, largest rho per z
   double* io = nullptr;
   int64_t io_n = 0;
   bool have_resid = false;
@@ -955,6 +984,11 @@ struct Engine : EngineBase {
     if ((s = put_conv(&deg_l, P.deg_l))) return s;
     if ((s = put(&upos, P.upos))) return s;
     if ((s = put(&uz, P.uz))) return s;
+    weighted = P.weighted;
+    if (weighted) {
+      if ((s = put_conv(&wz, P.wz))) return s;
+      if ((s = put_conv(&rmz, P.rmz))) return s;
+    }
     if ((s = alloc(&bmx, xblocks))) return s;
     if ((s = alloc(&bmz, zblocks))) return s;
     io_n = std::max(n_slots, nz);
@@ -1043,6 +1077,8 @@ struct Engine : EngineBase {
     a.w_stride = w_stride;
     a.w_base = w_base;
     a.l_base = l_base;
+    a.wz = wz;
+    a.rmz = rmz;
     a.zin = z[zc];
     a.zout = z[zc ^ 1];
     a.blockmax = bmz;
@@ -1200,7 +1236,8 @@ struct Engine : EngineBase {
     for (T v : hx) a = std::max(a, v);
     for (T v : hz) b = std::max(b, v);
     *r = (double)a;
-    *s = (double)b / (double)inv_rho;
+    // weighted graphs scale each variable's change by its largest rho in the kernel
+    *s = weighted ? (double)b : (double)b / (double)inv_rho;
     return ADMM_OK;
   }
 
@@ -1296,6 +1333,17 @@ admm_status admm_graph_set_rho(admm_graph* g, double rho) {
   if (g->state != 0) return admmi::set_err(ADMM_E_STATE, "graph already finalized");
   if (!(rho > 0.0) || !std::isfinite(rho)) return admmi::set_err(ADMM_E_ARG, "rho must be > 0");
   g->rho = rho;
+  return ADMM_OK;
+}
+
+admm_status admm_graph_set_group_rho(admm_graph* g, int32_t group, double rho) {
+  admmi::clear_err();
+  if (admm_status s = check_graph(g)) return s;
+  if (g->state != 0) return admmi::set_err(ADMM_E_STATE, "graph already finalized");
+  if (group < 0 || group >= (int32_t)g->groups.size())
+    return admmi::set_err(ADMM_E_ARG, "group %d out of range (%d groups)", group, (int)g->groups.size());
+  if (!(rho > 0.0) || !std::isfinite(rho)) return admmi::set_err(ADMM_E_ARG, "rho must be > 0");
+  g->groups[group].rho = rho;
   return ADMM_OK;
 }
 

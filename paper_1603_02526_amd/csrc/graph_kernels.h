@@ -65,6 +65,7 @@ struct BucketDesc {
   int64_t dst_off;      // index-buffer offset of the contribution destinations
   int64_t idx_off;      // offset in the int32 index buffer
   int64_t par_off;      // element offset in the parameter buffer
+  double irho;          // 1 / rho of this bucket's edges
 };
 
 template <typename T>
@@ -100,6 +101,8 @@ struct ZArgs {
   const T* zin;
   T* zout;
   T* blockmax;
+  const T* wz;            // per contribution position: its edge's rho (null: all equal)
+  const T* rmz;           // per z scalar: the largest rho of its edges (with wz)
   int32_t check;
 };
 
@@ -825,7 +828,7 @@ __device__ __forceinline__ void xpass_hinge(const XArgs<T>& a, const BucketDesc&
       dot += ns;
     }
     const T tau = tmin(C, tmax(T(0), (T(1) - dot) * iD));
-    const T st = tau * a.inv_rho;
+    const T st = tau * (T)b.irho;
     const T xb = nb + st * y;
     const T mnb = xb + ub;
     const bool shared_b = !UNIF && b.ub;
@@ -1220,7 +1223,11 @@ __device__ __forceinline__ void zpass_block(ZArgs<T> a, int blk) {
   if (blk < a.n_b) {
     const int64_t o1 = a.rng_b[2 * blk + 1];
     T s = T(0);
-    for (int64_t j = a.rng_b[2 * blk] + threadIdx.x; j < o1; j += NT) s += a.pool[j];
+    if (a.wz) {
+      for (int64_t j = a.rng_b[2 * blk] + threadIdx.x; j < o1; j += NT) s += a.wz[j] * a.pool[j];
+    } else {
+      for (int64_t j = a.rng_b[2 * blk] + threadIdx.x; j < o1; j += NT) s += a.pool[j];
+    }
     s = admmi::wave_sum(s);
     if ((threadIdx.x & 63) == 0) zred[threadIdx.x >> 6] = s;
     __syncthreads();
@@ -1231,7 +1238,7 @@ __device__ __forceinline__ void zpass_block(ZArgs<T> a, int blk) {
       const int zi = a.var_b[blk];
       const T zn = t / a.deg_b[blk];
       a.zout[zi] = zn;
-      if (a.check) dmax = tabs(zn - a.zin[zi]);
+      if (a.check) dmax = tabs(zn - a.zin[zi]) * (a.rmz ? a.rmz[zi] : T(1));
     }
   } else if (blk < a.n_b + a.nb_w) {
     const int sl = threadIdx.x & (ZSEG - 1);
@@ -1240,11 +1247,20 @@ __device__ __forceinline__ void zpass_block(ZArgs<T> a, int blk) {
     T s = T(0);
     if (ok) {
       if (a.w_stride) {
-        const T* p = a.pool + a.w_base + k * a.w_stride;
-        for (int64_t j = sl; j < a.w_stride; j += ZSEG) s += p[j];
+        const int64_t o = a.w_base + k * a.w_stride;
+        const T* p = a.pool + o;
+        if (a.wz) {
+          for (int64_t j = sl; j < a.w_stride; j += ZSEG) s += a.wz[o + j] * p[j];
+        } else {
+          for (int64_t j = sl; j < a.w_stride; j += ZSEG) s += p[j];
+        }
       } else {
         const int64_t o1 = a.rng_w[2 * k + 1];
-        for (int64_t j = a.rng_w[2 * k] + sl; j < o1; j += ZSEG) s += a.pool[j];
+        if (a.wz) {
+          for (int64_t j = a.rng_w[2 * k] + sl; j < o1; j += ZSEG) s += a.wz[j] * a.pool[j];
+        } else {
+          for (int64_t j = a.rng_w[2 * k] + sl; j < o1; j += ZSEG) s += a.pool[j];
+        }
       }
     }
     s = admmi::row16_sum(s);
@@ -1252,21 +1268,29 @@ __device__ __forceinline__ void zpass_block(ZArgs<T> a, int blk) {
       const int zi = a.var_w[k];
       const T zn = s / a.deg_w[k];
       a.zout[zi] = zn;
-      if (a.check) dmax = tabs(zn - a.zin[zi]);
+      if (a.check) dmax = tabs(zn - a.zin[zi]) * (a.rmz ? a.rmz[zi] : T(1));
     }
   } else {
     const int64_t k = (int64_t)(blk - a.n_b - a.nb_w) * NT + threadIdx.x;
     if (k < a.n_l) {
       const int zi = a.var_l[k];
       const T d = a.deg_l[k];
-      const T* p = a.pool + a.l_base + k * LANE_MAX;
-      T s = p[0];
+      const int64_t o = a.l_base + k * LANE_MAX;
+      const T* p = a.pool + o;
+      T s;
+      if (a.wz) {
+        s = a.wz[o] * p[0];
 #pragma unroll
-      for (int j = 1; j < LANE_MAX; ++j) s += p[j];
+        for (int j = 1; j < LANE_MAX; ++j) s += a.wz[o + j] * p[j];
+      } else {
+        s = p[0];
+#pragma unroll
+        for (int j = 1; j < LANE_MAX; ++j) s += p[j];
+      }
       T zn = a.zin[zi];
       if (d > T(0)) zn = s / d;
       a.zout[zi] = zn;
-      if (a.check) dmax = tabs(zn - a.zin[zi]);
+      if (a.check) dmax = tabs(zn - a.zin[zi]) * (a.rmz ? a.rmz[zi] : T(1));
     }
   }
   if (a.check) block_max_store(dmax, a.blockmax);

@@ -130,6 +130,23 @@ def test_copies_svm_layout():
     assert inf["n_contributions"] == p.n_slots - N + (N + 255) // 256
 
 
+def test_group_rho_state_and_radius_check():
+    g = A.Graph([2, 1])
+    g.add_factors("radius", [[1]], [0.5], shared=True)
+    g.set_group_rho(0, 0.4)                     # the group's rho must exceed gamma
+    _expect(A.E_NUMERIC, g.finalize, 0)
+    g = A.Graph([2, 1])
+    g.add_factors("radius", [[1]], [0.5], shared=True)
+    g.set_group_rho(0, 0.9)
+    g.set_rho(0.3)                              # the graph's rho no longer applies to it
+    assert _finalize_cpu(g) in (A.OK, A.E_NO_DEVICE)
+    p = W.packing(5, "square", 0.1, seed=9)
+    p.groups[2] = W.FactorGroup(p.groups[2].kind, p.groups[2].var_ids, p.groups[2].params,
+                                p.groups[2].shared, alpha=1.5)
+    with pytest.raises(ValueError):
+        A.Graph.from_problem(p, device=None)   # one alpha for all edges
+
+
 def test_incomplete_pairs_fall_back_to_general_layout():
     p = W.packing(12, "square", 0.05, seed=2)
     g0 = p.groups[0]
@@ -166,6 +183,12 @@ def test_validation_errors():
     _expect(A.E_ARG, g.add_factors, "margin", [[1, 0, 2]], [[1.0, 1.0]])        # dims (1,2,1)
     _expect(A.E_ARG, g.add_factors, "equal", [[0, 1]])                          # dims 2 vs 1
     _expect(A.E_ARG, g.add_factors, "minerr", [[1]], [-1.0], True)              # lambda < 0
+    g = A.Graph([1, 1])
+    g.add_factors("quad", [[0], [1]], [2.0], True)
+    _expect(A.E_ARG, g.set_group_rho, 1, 2.0)                             # no group 1
+    _expect(A.E_ARG, g.set_group_rho, 0, 0.0)                             # rho <= 0
+    _expect(A.E_ARG, g.set_group_rho, -1, 2.0)
+    g.set_group_rho(0, 2.0)
     _expect(A.E_ARG, A.Graph, [1, 0])                                      # dim 0
     _expect(A.E_ARG, A.Graph, [1], 7)                                      # precision
     g = A.Graph([1])

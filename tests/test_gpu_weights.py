@@ -1,0 +1,100 @@
+"""GPU parity with per-group edge weights rho (Algorithm 2's rho_(a,b),
+constant over each group of factors): the z-update is the rho-weighted mean
+and the dual residual weighs each variable by its largest rho.  Every layout
+is covered: dense pair tiles with the sparse pair state (FP32) and the
+general pair layout, shared-variable hinge partials, the copies graph's
+shared-bias partials, separable slots, linear dynamics; both drivers."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from paper_1603_02526_amd import admm as A
+from tests.helpers import rel, slot_z
+from tests.test_gpu_graph import _check, _conditioning
+
+pytestmark = pytest.mark.gpu
+
+FP32, FP64 = A.FP32, A.FP64
+
+
+def _weighted(p, rhos):
+    groups = [dataclasses.replace(g, rho=rhos.get(i)) for i, g in enumerate(p.groups)]
+    return dataclasses.replace(p, groups=groups)
+
+
+def _cases():
+    inst = W.mpc_batch(1, seed=46)[0]
+    inst.T = 20
+    return {
+        "packing_200": _weighted(W.packing(200, "square", 0.02, seed=47), {1: 2.0, 2: 3.0}),
+        "packing_tri10": _weighted(W.workload("packing_tri10"), {0: 1.5, 1: 2.0}),
+        "svm_3000_d6": _weighted(W.svm(3000, 6, seed=48), {0: 0.6, 1: 2.5}),
+        "svm_copies_300_d4": _weighted(W.svm_copies(300, 4, seed=49), {0: 1.5, 1: 0.8, 3: 2.0}),
+        "mpc": _weighted(W.mpc_graph(inst), {0: 2.0, 1: 2.0, 2: 0.5, 3: 1.3}),
+    }
+
+
+def _slot_rho(p):
+    out = []
+    for g in p.groups:
+        r = p.rho if g.rho is None else g.rho
+        out += [r] * int(p.var_dims[g.var_ids].sum())
+    return np.asarray(out)
+
+
+@pytest.mark.parametrize("name", ["packing_200", "packing_tri10", "svm_3000_d6",
+                                  "svm_copies_300_d4", "mpc"])
+@pytest.mark.parametrize("prec,iters,tol", [(FP64, 40, 1e-9), (FP32, 30, 1e-4)])
+@pytest.mark.parametrize("driver", [A.DRIVER_LAUNCHES, A.DRIVER_RESIDENT])
+def test_weighted_parity(name, prec, iters, tol, driver):
+    p = _cases()[name]
+    if name == "packing_200":
+        # random overlapping disks are chaotic: shorter horizons keep the
+        # oracle's own rounding sensitivity far below the tolerance
+        iters = 15 if prec == FP64 else 6
+    try:
+        g = A.Graph.from_problem(p, precision=prec, driver=driver)
+    except A.AdmmError as e:
+        assert driver == A.DRIVER_RESIDENT and e.status == A.E_UNSUPPORTED
+        pytest.skip("graph too large for the resident driver")
+    sens = _conditioning(p, iters, prec)
+    assert sens < tol / 20, sens
+    o = O.OracleGraph(p)
+    g.run(iters)
+    o.run(iters)
+    _check(g, o, tol)
+    # residuals are maxima of differences of z-sized quantities: their error
+    # scales with |z|
+    (r, s), (ro, so) = g.residuals(), o.residuals()
+    zmax = np.max(np.abs(o.z)) + 1.0
+    assert abs(r - ro) <= tol * zmax, (r, ro)
+    assert abs(s - so) <= tol * zmax * max(1.0, max(q.rho or 1.0 for q in p.groups)), (s, so)
+    # one step from a common state, element by element, and the weighted
+    # duals around every variable summing to zero
+    z, u = g.z(), g.u()
+    g.set_state(z, u)
+    o.set_state(z, u)
+    g.run(1)
+    o.run(1)
+    _check(g, o, 1e-12 if prec == FP64 else 1e-5)
+    sz = slot_z(p)
+    w = _slot_rho(p)
+    du = np.bincount(sz, weights=w * g.u(), minlength=p.n_scalars)
+    scale = np.bincount(sz, weights=w * (np.abs(g.u()) + np.abs(g.z()[sz])),
+                        minlength=p.n_scalars) + 1e-30
+    assert np.max(np.abs(du) / scale) < (1e-12 if prec == FP64 else 1e-5)
+
+
+def test_unit_group_weights_change_nothing():
+    """Group weights equal to the graph's rho keep the unweighted path: the
+    same iterates bit for bit."""
+    p = W.packing(60, "square", 0.05, seed=50)
+    q = _weighted(p, {0: 1.0, 1: 1.0, 2: 1.0})
+    a = A.Graph.from_problem(p, precision=FP32)
+    b = A.Graph.from_problem(q, precision=FP32)
+    a.run(20)
+    b.run(20)
+    assert np.array_equal(a.z(), b.z()) and np.array_equal(a.u(), b.u())
