@@ -129,9 +129,9 @@ admm_status admm_graph_add_factors(admm_graph* g, int32_t kind,
                                    const double* params, int32_t param_len,
                                    int32_t shared_params);
 
-/* rho (> 0) and alpha (> 0) of the edges (Alg. 2).  Defaults 1 and 1.
- * alpha is one value for all edges; rho is the value of every edge whose
- * group has none of its own (below).  Only before finalize. */
+/* rho (> 0) and alpha (> 0) of the edges (Alg. 2).  Defaults 1 and 1:
+ * the values of every edge whose group has none of its own (below).  Only
+ * before finalize. */
 admm_status admm_graph_set_rho(admm_graph* g, double rho);
 admm_status admm_graph_set_alpha(admm_graph* g, double alpha);
 
@@ -144,6 +144,11 @@ admm_status admm_graph_set_alpha(admm_graph* g, double alpha);
  * edges.  ADMM_E_ARG for a group index out of range or rho <= 0; only
  * before finalize. */
 admm_status admm_graph_set_group_rho(admm_graph* g, int32_t group, double rho);
+
+/* alpha (> 0) of the edges of one group of factors (u += alpha (x - z) on
+ * each of them, Algorithm 2).  When every edge's alpha is 1 the library
+ * keeps m alone per edge; otherwise m and x.  Errors as above. */
+admm_status admm_graph_set_group_alpha(admm_graph* g, int32_t group, double alpha);
 
 /* Layout options, set before finalize.
  *  ADMM_OPT_PAIR_ROWS: disks per row of a dense pair tile (16, 32 or 64;

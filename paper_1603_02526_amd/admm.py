@@ -80,6 +80,7 @@ def lib():
         _sig(L, "admm_graph_set_rho", st, [VP, ctypes.c_double])
         _sig(L, "admm_graph_set_alpha", st, [VP, ctypes.c_double])
         _sig(L, "admm_graph_set_group_rho", st, [VP, ctypes.c_int32, ctypes.c_double])
+        _sig(L, "admm_graph_set_group_alpha", st, [VP, ctypes.c_int32, ctypes.c_double])
         _sig(L, "admm_graph_finalize", st, [VP, ctypes.c_int32])
         _sig(L, "admm_graph_set_option", st, [VP, ctypes.c_int32, ctypes.c_int64])
         _sig(L, "admm_graph_info_get", st, [VP, ctypes.POINTER(GraphInfo)])
@@ -158,6 +159,10 @@ class Graph:
         """rho of the edges of the group-th add_factors call."""
         check(lib().admm_graph_set_group_rho(self._h, int(group), float(rho)))
 
+    def set_group_alpha(self, group: int, alpha: float):
+        """alpha of the edges of the group-th add_factors call."""
+        check(lib().admm_graph_set_group_alpha(self._h, int(group), float(alpha)))
+
     def set_alpha(self, alpha: float):
         check(lib().admm_graph_set_alpha(self._h, float(alpha)))
 
@@ -229,8 +234,7 @@ class Graph:
             if getattr(grp, "rho", None) is not None:
                 g.set_group_rho(i, grp.rho)
             if getattr(grp, "alpha", None) is not None:
-                raise ValueError("the library takes one alpha for all edges; "
-                                 "per-group alpha is not supported")
+                g.set_group_alpha(i, grp.alpha)
         g.set_rho(problem.rho if rho is None else rho)
         g.set_alpha(problem.alpha if alpha is None else alpha)
         if pair_rows:

@@ -37,6 +37,7 @@ struct Group {
   int32_t kind, n, arity, plen;
   bool shared;
   double rho = 0.0;            // rho of this group's edges (0: the graph's)
+  double alpha = 0.0;          // alpha of this group's edges (0: the graph's)
   std::vector<int32_t> vids;   // [n * arity]
   std::vector<double> params;  // [n * plen] or [plen]
   const double* prm(int64_t f) const {
@@ -59,6 +60,8 @@ struct Plan {
   bool weighted = false;        // groups with different rho: weighted z-sums
   std::vector<double> wz;       // weighted: relative rho of every contribution position
   std::vector<double> rmz;      // weighted: per z scalar, the largest rho of its edges
+  bool alpha_one = true;        // every edge has alpha = 1 (m-only state)
+  std::vector<double> ualpha;   // groups with different alpha: alpha per user slot
   std::vector<int64_t> upos;    // user slot -> pool position of m
   std::vector<int32_t> uz;      // user slot -> z index
   int64_t xblocks = 0;
@@ -271,8 +274,20 @@ bool hinge_uniform(const Group& gr) {
 }
 
 // Build the device layout.  Validation errors return non-OK.
+// True when every edge's alpha is 1 (the graph's or its group's).
+bool all_alpha_one(const admm_graph& g) {
+  for (const Group& gr : g.groups)
+    if ((gr.alpha > 0.0 ? gr.alpha : g.alpha) != 1.0) return false;
+  return g.groups.empty() ? g.alpha == 1.0 : true;
+}
+
 admm_status build_plan(admm_graph& g, Plan& P, bool no_tiles) {
   P = Plan();
+  P.alpha_one = all_alpha_one(g);
+  bool alpha_mixed = false;
+  for (const Group& gr : g.groups)
+    if (gr.alpha > 0.0 && gr.alpha != g.alpha) alpha_mixed = true;
+  if (alpha_mixed) P.ualpha.assign(g.n_slots, g.alpha);
   P.no_tiles = no_tiles;
   // Every contribution to a z scalar, in emission order: z index and the
   // index-buffer slot that will receive its position in the z-major buffer.
@@ -292,6 +307,8 @@ admm_status build_plan(admm_graph& g, Plan& P, bool no_tiles) {
     // graph without group weights, so such graphs keep their unweighted sums
     const double rw = rg / g.rho;
     if (rg != g.rho) P.weighted = true;
+    const double ag = gr.alpha > 0.0 ? gr.alpha : g.alpha;
+    const int64_t us0 = us;
     std::string why;
     int32_t nn = 0, mm = 0;
     if (!kind_dim_ok(g, gr, why, nn, mm)) return admmi::set_err(ADMM_E_ARG, "%s", why.c_str());
@@ -352,7 +369,7 @@ admm_status build_plan(admm_graph& g, Plan& P, bool no_tiles) {
         b.ent_aff = aff ? 1 : 0;
         b.ent_base = aff ? ezc[0] : 0;
       }
-      b.sparse = (g.precision == ADMM_FP32 && g.alpha == 1.0 &&
+      b.sparse = (g.precision == ADMM_FP32 && P.alpha_one &&
                   g.pair_state != ADMM_PAIR_STATE_DENSE) ? 1 : 0;
       b.flag0 = P.n_flags;
       if (b.sparse) P.n_flags += b.n * NT;
@@ -688,6 +705,9 @@ admm_status build_plan(admm_graph& g, Plan& P, bool no_tiles) {
       P.layout_idx_bytes += (int64_t)gr.n * gr.arity * 4;
     }
     b.irho = 1.0 / rg;
+    b.alpha = ag;
+    if (!P.ualpha.empty())
+      for (int64_t q = us0; q < us; ++q) P.ualpha[q] = ag;
     P.bt.push_back(b);
     em_rho.push_back({em.size(), rw});
   }
@@ -830,6 +850,7 @@ struct Engine : EngineBase {
   int32_t* uz = nullptr;
   T *bmx = nullptr, *bmz = nullptr;
   bool weighted = false;           // groups with different rho
+  T* ualpha = nullptr;             // groups with different alpha: alpha per user slot
   T *wz = nullptr, *rmz = nullptr;  // weighted: rho per contribution position, largest rho per z
   double* io = nullptr;
   int64_t io_n = 0;
@@ -931,7 +952,8 @@ struct Engine : EngineBase {
 
   admm_status upload(const Plan& P, const std::vector<double>& z0, double rho,
                      double alpha_) override {
-    alpha1 = (alpha_ == 1.0);
+    alpha1 = P.alpha_one;
+    (void)alpha_;
     alpha = (T)alpha_;
     inv_rho = (T)(1.0 / rho);
     nb = (int)P.bt.size();
@@ -984,6 +1006,8 @@ struct Engine : EngineBase {
     if ((s = put_conv(&deg_l, P.deg_l))) return s;
     if ((s = put(&upos, P.upos))) return s;
     if ((s = put(&uz, P.uz))) return s;
+    if (!P.ualpha.empty())
+      if ((s = put_conv(&ualpha, P.ualpha))) return s;
     weighted = P.weighted;
     if (weighted) {
       if ((s = put_conv(&wz, P.wz))) return s;
@@ -1214,10 +1238,10 @@ struct Engine : EngineBase {
     if (g) {
       if (alpha1)
         get_slots_kernel<T, true><<<g, 256, 0, st>>>(n_slots, upos, uz, pool, z[zc], xdelta, alpha,
-                                                      which, io);
+                                                      nullptr, which, io);
       else
         get_slots_kernel<T, false><<<g, 256, 0, st>>>(n_slots, upos, uz, pool, z[zc], xdelta,
-                                                       alpha, which, io);
+                                                       alpha, ualpha, which, io);
     }
     ADMM_HIP(hipGetLastError());
     ADMM_HIP(hipMemcpyAsync(out, io, n_slots * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -1347,6 +1371,17 @@ admm_status admm_graph_set_group_rho(admm_graph* g, int32_t group, double rho) {
   return ADMM_OK;
 }
 
+admm_status admm_graph_set_group_alpha(admm_graph* g, int32_t group, double alpha) {
+  admmi::clear_err();
+  if (admm_status s = check_graph(g)) return s;
+  if (g->state != 0) return admmi::set_err(ADMM_E_STATE, "graph already finalized");
+  if (group < 0 || group >= (int32_t)g->groups.size())
+    return admmi::set_err(ADMM_E_ARG, "group %d out of range (%d groups)", group, (int)g->groups.size());
+  if (!(alpha > 0.0) || !std::isfinite(alpha)) return admmi::set_err(ADMM_E_ARG, "alpha must be > 0");
+  g->groups[group].alpha = alpha;
+  return ADMM_OK;
+}
+
 admm_status admm_graph_set_alpha(admm_graph* g, double alpha) {
   admmi::clear_err();
   if (admm_status s = check_graph(g)) return s;
@@ -1417,11 +1452,11 @@ admm_status admm_graph_finalize(admm_graph* g, int32_t device) {
   I.n_pair_tiles = P.n_pair_tiles;
   I.n_contributions = P.n_zc;
   I.precision = g->precision;
-  I.alpha_is_one = g->alpha == 1.0;
+  I.alpha_is_one = P.alpha_one;
   I.state_bytes = (P.zc_span + 2 * P.n_m) * es;
   // algorithmic: state read + write per slot (m; plus x when alpha != 1) and
   // per-factor prox data; layout: indices, partial sums and their reads.
-  I.algo_bytes_per_iter = P.algo_elems * es * (g->alpha == 1.0 ? 1 : 2);
+  I.algo_bytes_per_iter = P.algo_elems * es * (P.alpha_one ? 1 : 2);
   I.layout_bytes_per_iter = P.layout_elems * es + P.layout_idx_bytes;
   I.driver = P.resident ? ADMM_DRIVER_RESIDENT : ADMM_DRIVER_LAUNCHES;
   I.sparse_pair_state = P.n_flags > 0 ? 1 : 0;
@@ -1442,7 +1477,7 @@ admm_status admm_graph_finalize(admm_graph* g, int32_t device) {
     eng.reset(e);
   }
   if (g->plan.resident) {
-    if (admm_status s = eng->resident_check(P, g->nz, g->alpha == 1.0)) {
+    if (admm_status s = eng->resident_check(P, g->nz, P.alpha_one)) {
       if (g->driver == ADMM_DRIVER_RESIDENT) return s;
       admmi::clear_err();
       g->plan.resident = false;  // auto: the same plan runs with launches

@@ -66,6 +66,7 @@ struct BucketDesc {
   int64_t idx_off;      // offset in the int32 index buffer
   int64_t par_off;      // element offset in the parameter buffer
   double irho;          // 1 / rho of this bucket's edges
+  double alpha;         // alpha of this bucket's edges
 };
 
 template <typename T>
@@ -259,7 +260,7 @@ __device__ __forceinline__ void xpass_pair(const XArgs<T>& a, const BucketDesc& 
       for (int s = 0; s < 6; ++s) {
         T xo = T(0);
         if constexpr (!A1) xo = xt[s * TSZ + p];
-        state_un<T, A1>(mv[s], xo, zz[s], a.alpha, u[s], v[s]);
+        state_un<T, A1>(mv[s], xo, zz[s], (T)b.alpha, u[s], v[s]);
       }
       prox_nonoverlap(v);
       T mn[6];
@@ -795,7 +796,7 @@ __device__ __forceinline__ void xpass_hinge(const XArgs<T>& a, const BucketDesc&
       if constexpr (MODE == PM_RESID) {
         if (valid) rmax = tmax(rmax, tabs(xo - zk));
       } else {
-        state_un<T, A1>(mk, xo, zk, a.alpha, uv[k], nv[k]);
+        state_un<T, A1>(mk, xo, zk, (T)b.alpha, uv[k], nv[k]);
         ya[k] = P[k * nfp + ff];
         dot += nv[k] * ya[k];
       }
@@ -819,12 +820,12 @@ __device__ __forceinline__ void xpass_hinge(const XArgs<T>& a, const BucketDesc&
     return;
   } else {
     T ub, nb;
-    state_un<T, A1>(mb, xob, zb, a.alpha, ub, nb);
+    state_un<T, A1>(mb, xob, zb, (T)b.alpha, ub, nb);
     const T y = P[d * nfp + ff], C = P[(d + 1) * nfp + ff], iD = P[(d + 2) * nfp + ff];
     dot += y * nb;
     T us = T(0), ns = T(0);
     if (margin) {
-      state_un<T, A1>(ms, xos, zs, a.alpha, us, ns);
+      state_un<T, A1>(ms, xos, zs, (T)b.alpha, us, ns);
       dot += ns;
     }
     const T tau = tmin(C, tmax(T(0), (T(1) - dot) * iD));
@@ -911,7 +912,7 @@ __device__ __forceinline__ void xpass_slot(const XArgs<T>& a, const BucketDesc& 
       T xo = T(0);
       if constexpr (!A1) xo = X[s];
       T u, n;
-      state_un<T, A1>(M[s], xo, zv, a.alpha, u, n);
+      state_un<T, A1>(M[s], xo, zv, (T)b.alpha, u, n);
       const T p0 = P[s];
       T x;
       if (b.kind == KD_BOX) {
@@ -960,7 +961,7 @@ __device__ __forceinline__ void gen_gather(const XArgs<T>& a, const BucketDesc& 
           if constexpr (MODE == PM_RESID) {
             rmax = tmax(rmax, tabs(xo - zv));
           } else {
-            state_un<T, A1>(mv, xo, zv, a.alpha, u[s], v[s]);
+            state_un<T, A1>(mv, xo, zv, (T)b.alpha, u[s], v[s]);
           }
           ++s;
         }
@@ -1060,7 +1061,7 @@ __device__ __forceinline__ void xpass_lindyn(const XArgs<T>& a, const BucketDesc
         if constexpr (MODE == PM_RESID) {
           rmax = tmax(rmax, tabs(xo - zv));
         } else {
-          state_un<T, A1>(M[j * nfp + f], xo, zv, a.alpha, ua[j], va[j]);
+          state_un<T, A1>(M[j * nfp + f], xo, zv, (T)b.alpha, ua[j], va[j]);
         }
       }
     }
@@ -1073,7 +1074,7 @@ __device__ __forceinline__ void xpass_lindyn(const XArgs<T>& a, const BucketDesc
         if constexpr (MODE == PM_RESID) {
           rmax = tmax(rmax, tabs(xo - zv));
         } else {
-          state_un<T, A1>(M[(k + r) * nfp + f], xo, zv, a.alpha, ub[r], vb[r]);
+          state_un<T, A1>(M[(k + r) * nfp + f], xo, zv, (T)b.alpha, ub[r], vb[r]);
         }
       }
     }
@@ -1408,7 +1409,7 @@ __global__ void set_state_kernel(int64_t ns, const int64_t* upos, const int32_t*
 template <typename T, bool A1>
 __global__ void get_slots_kernel(int64_t ns, const int64_t* upos, const int32_t* uz,
                                  const T* pool, const T* z, int64_t xdelta, T alpha,
-                                 int which, double* out) {
+                                 const T* ualpha, int which, double* out) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= ns) return;
   const int64_t p = upos[i];
@@ -1422,7 +1423,7 @@ __global__ void get_slots_kernel(int64_t ns, const int64_t* upos, const int32_t*
     u = pool[p] - zv;
   } else {
     const T xo = pool[p + xdelta];
-    u = (pool[p] - xo) + alpha * (xo - zv);
+    u = (pool[p] - xo) + (ualpha ? ualpha[i] : alpha) * (xo - zv);
   }
   out[i] = (double)u;
 }

@@ -140,11 +140,17 @@ def test_group_rho_state_and_radius_check():
     g.set_group_rho(0, 0.9)
     g.set_rho(0.3)                              # the graph's rho no longer applies to it
     assert _finalize_cpu(g) in (A.OK, A.E_NO_DEVICE)
+    g = A.Graph([1])
+    g.add_factors("quad", [[0]], [2.0], True)
+    _expect(A.E_ARG, g.set_group_alpha, 0, -1.0)
+    _expect(A.E_ARG, g.set_group_alpha, 3, 1.5)
+    # a group alpha other than 1 switches the whole graph to the (m, x) state
     p = W.packing(5, "square", 0.1, seed=9)
     p.groups[2] = W.FactorGroup(p.groups[2].kind, p.groups[2].var_ids, p.groups[2].params,
                                 p.groups[2].shared, alpha=1.5)
-    with pytest.raises(ValueError):
-        A.Graph.from_problem(p, device=None)   # one alpha for all edges
+    g = A.Graph.from_problem(p, device=None)
+    assert _finalize_cpu(g) in (A.OK, A.E_NO_DEVICE)
+    assert g.info()["alpha_is_one"] == 0
 
 
 def test_incomplete_pairs_fall_back_to_general_layout():

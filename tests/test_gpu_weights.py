@@ -20,8 +20,10 @@ pytestmark = pytest.mark.gpu
 FP32, FP64 = A.FP32, A.FP64
 
 
-def _weighted(p, rhos):
-    groups = [dataclasses.replace(g, rho=rhos.get(i)) for i, g in enumerate(p.groups)]
+def _weighted(p, rhos, alphas=None):
+    alphas = alphas or {}
+    groups = [dataclasses.replace(g, rho=rhos.get(i), alpha=alphas.get(i))
+              for i, g in enumerate(p.groups)]
     return dataclasses.replace(p, groups=groups)
 
 
@@ -34,6 +36,11 @@ def _cases():
         "svm_3000_d6": _weighted(W.svm(3000, 6, seed=48), {0: 0.6, 1: 2.5}),
         "svm_copies_300_d4": _weighted(W.svm_copies(300, 4, seed=49), {0: 1.5, 1: 0.8, 3: 2.0}),
         "mpc": _weighted(W.mpc_graph(inst), {0: 2.0, 1: 2.0, 2: 0.5, 3: 1.3}),
+        # group alpha as well (the (m, x) state, alpha per bucket and per exported slot)
+        "packing_tri10_alpha": _weighted(W.workload("packing_tri10"), {1: 2.0},
+                                         {0: 1.5, 2: 0.7}),
+        "svm_3000_d6_alpha": _weighted(W.svm(3000, 6, seed=48), {0: 0.6}, {0: 1.3, 1: 0.8}),
+        "mpc_alpha": _weighted(W.mpc_graph(inst), {2: 0.5}, {0: 1.2, 1: 1.2, 3: 0.9}),
     }
 
 
@@ -46,7 +53,8 @@ def _slot_rho(p):
 
 
 @pytest.mark.parametrize("name", ["packing_200", "packing_tri10", "svm_3000_d6",
-                                  "svm_copies_300_d4", "mpc"])
+                                  "svm_copies_300_d4", "mpc", "packing_tri10_alpha",
+                                  "svm_3000_d6_alpha", "mpc_alpha"])
 @pytest.mark.parametrize("prec,iters,tol", [(FP64, 40, 1e-9), (FP32, 30, 1e-4)])
 @pytest.mark.parametrize("driver", [A.DRIVER_LAUNCHES, A.DRIVER_RESIDENT])
 def test_weighted_parity(name, prec, iters, tol, driver):
@@ -80,6 +88,9 @@ def test_weighted_parity(name, prec, iters, tol, driver):
     g.run(1)
     o.run(1)
     _check(g, o, 1e-12 if prec == FP64 else 1e-5)
+    if any(q.alpha is not None for q in p.groups):
+        assert g.info()["alpha_is_one"] == 0
+        return          # the zero weighted dual sums need one alpha per variable
     sz = slot_z(p)
     w = _slot_rho(p)
     du = np.bincount(sz, weights=w * g.u(), minlength=p.n_scalars)
