@@ -72,6 +72,8 @@ def lib(openmp: bool = False):
         L.orc_set_state.argtypes = [vp, dp, dp]
         L.orc_run.restype = ctypes.c_int
         L.orc_run.argtypes = [vp, ctypes.c_int, ctypes.c_double]
+        L.orc_run_region.restype = ctypes.c_int
+        L.orc_run_region.argtypes = [vp, ctypes.c_int, ctypes.c_double]
         for nm in ("orc_get_z", "orc_get_u", "orc_get_x", "orc_get_m"):
             getattr(L, nm).argtypes = [vp, dp]
         L.orc_get_slot_z.argtypes = [vp, lp]
@@ -153,8 +155,12 @@ class OracleGraph:
         else:
             self._L.orc_set_state(self._h, _dp(z), None)
 
-    def run(self, iters: int, tol: float = 0.0) -> int:
-        return int(self._L.orc_run(self._h, int(iters), float(tol)))
+    def run(self, iters: int, tol: float = 0.0, region: bool = False) -> int:
+        """Run Algorithm 2; region=True uses the one-parallel-region loop
+        structure (the paper's second CPU scheme) instead of one parallel
+        region per update.  Both give the same results bit for bit."""
+        fn = self._L.orc_run_region if region else self._L.orc_run
+        return int(fn(self._h, int(iters), float(tol)))
 
     def _get(self, fn, n):
         out = np.zeros(n)

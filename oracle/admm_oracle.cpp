@@ -463,6 +463,72 @@ void iterate(Graph& g) {
   g.r_dual = s;
 }
 
+// The whole run as one parallel region (the paper's second CPU scheme,
+// Sec. III-A): the threads live for every iteration, each update type is a
+// work-shared loop over its own index, and the barrier at the end of each
+// loop separates one update type from the next.  Every element gets the
+// same arithmetic in the same order as in iterate(), so the results equal
+// the serial ones bit for bit; the stopping test reads the two maxima after
+// the barrier that ends their loops, so every thread leaves at the same
+// iteration.  Returns the iterations done.
+int run_region(Graph& g, int max_iter, double tol) {
+  const long S = g.nslot;
+  const long NF = static_cast<long>(g.F.size());
+  if (g.lists_for != S) build_lists(g);
+  int done = max_iter;
+  double r = 0.0, s = 0.0;
+#pragma omp parallel
+  {
+    std::vector<int> dims;
+    for (int k = 1; k <= max_iter; ++k) {
+#pragma omp for schedule(static)
+      for (long e = 0; e < S; ++e) g.n[e] = g.z[g.slot_z[e]] - g.u[e];
+#pragma omp for schedule(dynamic, 256)
+      for (long i = 0; i < NF; ++i) {
+        const Factor& f = g.F[i];
+        dims.resize(f.vars.size());
+        for (size_t q = 0; q < f.vars.size(); ++q) dims[q] = g.dim[f.vars[q]];
+        const long s0 = f.slot[0];
+        prox_apply(f.kind, static_cast<int>(f.vars.size()), dims.data(),
+                   f.p.data(), static_cast<int>(f.p.size()), f.rho > 0.0 ? f.rho : g.rho,
+                   &g.n[s0], &g.x[s0]);
+      }
+#pragma omp for schedule(static)
+      for (long e = 0; e < S; ++e) g.m[e] = g.x[e] + g.u[e];
+#pragma omp single
+      {
+        g.zprev = g.z;
+        r = 0.0;
+        s = 0.0;
+      }
+#pragma omp for schedule(static)
+      for (long b = 0; b < g.nz; ++b) {
+        double num = 0.0, den = 0.0;
+        for (long q = g.zbeg[b]; q < g.zbeg[b + 1]; ++q) {
+          const long e = g.zedges[q];
+          num += g.erho[e] * g.m[e];
+          den += g.erho[e];
+        }
+        if (den > 0.0) g.z[b] = num / den;
+      }
+#pragma omp for schedule(static)
+      for (long e = 0; e < S; ++e) g.u[e] += g.ealpha[e] * (g.x[e] - g.z[g.slot_z[e]]);
+#pragma omp for schedule(static) reduction(max : r)
+      for (long e = 0; e < S; ++e) r = std::max(r, std::fabs(g.x[e] - g.z[g.slot_z[e]]));
+#pragma omp for schedule(static) reduction(max : s)
+      for (long b = 0; b < g.nz; ++b) s = std::max(s, g.vrho[b] * std::fabs(g.z[b] - g.zprev[b]));
+      if (tol > 0.0 && r <= tol && s <= tol) {
+#pragma omp single nowait
+        done = k;
+        break;
+      }
+    }
+  }
+  g.r_primal = r;
+  g.r_dual = s;
+  return done;
+}
+
 }  // namespace
 
 extern "C" {
@@ -567,6 +633,14 @@ int orc_run(void* h, int max_iter, double tol) {
     if (tol > 0.0 && g->r_primal <= tol && g->r_dual <= tol) return k;
   }
   return max_iter;
+}
+
+// orc_run with the one-region scheme (run_region); the same results.
+int orc_run_region(void* h, int max_iter, double tol) {
+  Graph* g = static_cast<Graph*>(h);
+  if (static_cast<long>(g->u.size()) != g->nslot) orc_set_state(h, g->z.data(), nullptr);
+  if (max_iter < 1) return 0;
+  return run_region(*g, max_iter, tol);
 }
 
 void orc_get_z(void* h, double* z) {

@@ -32,3 +32,23 @@ def test_openmp_build_is_bitwise_serial(name):
     ka = a.run(5000, tol=1e-6)
     kb = b.run(5000, tol=1e-6)
     assert ka == kb and np.array_equal(a.z, b.z)
+
+
+@pytest.mark.parametrize("name", ["packing_40", "svm_300_d4", "svm_copies_25_d3", "mpc"])
+def test_one_region_scheme_is_bitwise_serial(name):
+    """The paper's second CPU scheme (one parallel region for the whole run,
+    barriers between update types) also computes the serial iteration bit
+    for bit, stopping iteration included, in both builds."""
+    p = _cases()[name]
+    a = O.OracleGraph(p)
+    b = O.OracleGraph(p, openmp=True)
+    c = O.OracleGraph(p)
+    a.run(40)
+    b.run(40, region=True)
+    c.run(40, region=True)
+    for g in (b, c):
+        assert np.array_equal(a.z, g.z) and np.array_equal(a.u, g.u) and np.array_equal(a.x, g.x)
+        assert a.residuals() == g.residuals()
+    ka = a.run(5000, tol=1e-6)
+    kb = b.run(5000, tol=1e-6, region=True)
+    assert ka == kb and np.array_equal(a.z, b.z) and a.residuals() == b.residuals()
