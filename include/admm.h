@@ -99,7 +99,7 @@ typedef struct {
   int64_t layout_bytes_per_iter; /* index/partial bytes of one iteration */
   int32_t precision;           /* admm_precision */
   int32_t alpha_is_one;        /* 1: m-only state (alpha == 1) */
-  int32_t driver;              /* ADMM_DRIVER_LAUNCHES or ADMM_DRIVER_RESIDENT */
+  int32_t driver;              /* ADMM_DRIVER_LAUNCHES, _RESIDENT or _GRAPH */
   int32_t resident_lds_bytes;  /* LDS image of the resident driver (0 if unused) */
   int32_t sparse_pair_state;   /* 1: pair tiles keep unmoved pairs' m implicit */
   int32_t reserved_;
@@ -155,15 +155,22 @@ admm_status admm_graph_set_group_alpha(admm_graph* g, int32_t group, double alph
  *  0 = default, 64).  Each tile holds rows x 64 pairs and
  *  is one workgroup of the x-pass; results do not depend on the choice
  *  beyond the order of the z-sums.
- *  ADMM_OPT_DRIVER: how admm_run executes the iterations (Alg. 2 loop).
+ *  ADMM_OPT_DRIVER: how admm_run executes the iterations (the loop of
+ *  Algorithm 2; Sec. III runs each iteration as separate kernel launches).
  *  ADMM_DRIVER_LAUNCHES: one x-pass and one z-pass launch per iteration,
- *  enqueued back to back.  ADMM_DRIVER_RESIDENT: the whole run in one
- *  launch of one workgroup that keeps every per-iteration array in LDS;
- *  only for small graphs (no dense pair tiles, LDS image within the
- *  device's per-workgroup limit): finalize returns ADMM_E_UNSUPPORTED when
- *  the graph does not fit.  ADMM_DRIVER_AUTO (default): resident when the
- *  graph fits and has at most 64 x-pass plus z-pass blocks, else launches.
- *  The arithmetic of every step is the same in both drivers.
+ *  enqueued back to back.  ADMM_DRIVER_GRAPH: the same launches, recorded
+ *  once into a hipGraph of ADMM_OPT_GRAPH_BLOCK iterations (per starting z
+ *  buffer, at the first run that needs it) and replayed with one graph
+ *  launch per block; the last iteration of a run and any remainder are
+ *  launched directly.  ADMM_DRIVER_RESIDENT: the whole run in one launch of
+ *  one workgroup that keeps every per-iteration array in LDS; only for small
+ *  graphs (no dense pair tiles, LDS image within the device's per-workgroup
+ *  limit): finalize returns ADMM_E_UNSUPPORTED when the graph does not fit.
+ *  ADMM_DRIVER_AUTO (default): resident when the graph fits and has at most
+ *  64 x-pass plus z-pass blocks, else graph.  The arithmetic of every step
+ *  is the same in every driver, and launches and graph give identical bits.
+ *  ADMM_OPT_GRAPH_BLOCK: iterations per recorded block (even, 2..4096;
+ *  0 = default 32).
  *  ADMM_OPT_PAIR_STATE: per-edge state of dense pair tiles.  With alpha = 1
  *  a pair whose prox leaves n unchanged (no overlap) ends the iteration with
  *  m = z, the consensus it started from (Alg. 2: m = x + u, u = m_old - z,
@@ -174,24 +181,37 @@ admm_status admm_graph_set_group_alpha(admm_graph* g, int32_t group, double alph
  *  iteration; the last iteration of a run stores the state of every pair.
  *  ADMM_PAIR_STATE_DENSE reads and writes every pair's m every iteration
  *  (always the case in FP64 or with alpha != 1). */
-enum { ADMM_OPT_PAIR_ROWS = 1, ADMM_OPT_DRIVER = 2, ADMM_OPT_PAIR_STATE = 3 };
-enum { ADMM_DRIVER_AUTO = 0, ADMM_DRIVER_LAUNCHES = 1, ADMM_DRIVER_RESIDENT = 2 };
+enum { ADMM_OPT_PAIR_ROWS = 1, ADMM_OPT_DRIVER = 2, ADMM_OPT_PAIR_STATE = 3,
+       ADMM_OPT_GRAPH_BLOCK = 4 };
+enum { ADMM_DRIVER_AUTO = 0, ADMM_DRIVER_LAUNCHES = 1, ADMM_DRIVER_RESIDENT = 2,
+       ADMM_DRIVER_GRAPH = 3 };
 enum { ADMM_PAIR_STATE_AUTO = 0, ADMM_PAIR_STATE_DENSE = 1 };
 admm_status admm_graph_set_option(admm_graph* g, int32_t option, int64_t value);
 
-/* Validate, bucket factors by kind, build the device layout (edge-major
- * structure-of-arrays per bucket, dense pair tiles for complete pairwise
- * non-overlap buckets, per-variable contribution lists) and upload it to
- * `device`.  Sets z to 0 and u to 0.  Returns ADMM_E_NO_DEVICE (after full
- * validation) when no GPU is present, ADMM_E_NUMERIC when rho <= gamma for a
- * RADIUS factor. */
+/* Paper Sec. III: the step that copies the graph built on the host to the
+ * GPU once, before any iteration (graph construction and this copy are
+ * outside the timed iterations there too).  Validate, bucket factors by
+ * kind, build the device layout (edge-major structure-of-arrays per
+ * bucket, dense pair tiles for complete pairwise non-overlap buckets,
+ * per-variable contribution lists) and upload it to `device`; the handle
+ * owns every device buffer from here on.  Sets z to 0 and u to 0.  Returns
+ * ADMM_E_NO_DEVICE (after full validation) when no GPU is present,
+ * ADMM_E_NUMERIC when rho <= gamma for a RADIUS factor, ADMM_E_STATE when
+ * called twice, ADMM_E_OOM when a device allocation fails. */
 admm_status admm_graph_finalize(admm_graph* g, int32_t device);
 
+/* Counts and byte figures of a finalized graph (paper Sec. IV: the number
+ * of factors, edges and variables of each problem; here also the layout
+ * the library chose).  info: caller-owned struct, filled on success;
+ * ADMM_E_STATE before finalize. */
 admm_status admm_graph_info_get(const admm_graph* g, admm_graph_info* info);
 
-/* Set the iteration state from host arrays: z[n_scalars] in variable order
- * and u[n_slots] in user slot order (NULL: u = 0).  The next x-update uses
- * n = z - u. */
+/* Algorithm 2's initial state (Sec. II: the iteration starts from given z
+ * and u; n = z - u before the first x-update).  Set it from host arrays:
+ * z[n_scalars] in variable order and u[n_slots] in user slot order (NULL:
+ * u = 0); both are copied (double, converted to the working precision) and
+ * the stream is synchronised before return.  The next x-update uses
+ * n = z - u.  ADMM_E_STATE before finalize, ADMM_E_ARG for a NULL z. */
 admm_status admm_set_state(admm_graph* g, const double* z, const double* u,
                            void* stream);
 
@@ -208,8 +228,14 @@ admm_status admm_run(admm_graph* g, int32_t iters, void* stream);
 admm_status admm_run_profiled(admm_graph* g, int32_t iters, void* stream,
                               double* xpass_ms, double* zpass_ms);
 
-/* Copy results to host arrays (double).  z: [n_scalars] variable order;
- * u and x: [n_slots] user slot order (x of the last iteration run). */
+/* Paper Sec. III: after the iterations the z values are copied back from
+ * the GPU (the only per-solve transfer there; Sec. V reports its time).
+ * Copy results to caller-owned host arrays (double, widened from the
+ * working precision).  z: [n_scalars] variable order; u and x: [n_slots]
+ * user slot order (x of the last iteration run; u and x are the per-edge
+ * quantities of Algorithm 2, for inspection and for resuming a run through
+ * admm_set_state).  Synchronise the stream.  ADMM_E_STATE before finalize,
+ * ADMM_E_ARG for a NULL output. */
 admm_status admm_get_z(admm_graph* g, double* z, void* stream);
 admm_status admm_get_u(admm_graph* g, double* u, void* stream);
 admm_status admm_get_x(admm_graph* g, double* x, void* stream);
@@ -222,9 +248,14 @@ admm_status admm_get_residuals(admm_graph* g, double* r_primal,
                                double* r_dual, void* stream);
 
 /* Device address of z (working precision, variable order) for callers that
- * read it in place; valid until the next run or destroy. */
+ * read it in place (Sec. III's read-back of z without the copy); valid
+ * until the next run or destroy; the handle keeps ownership. */
 admm_status admm_z_device_ptr(admm_graph* g, void** z_dev);
 
+/* Release the handle and every device buffer it owns (the GPU-side graph of
+ * Sec. III).  NULL is accepted and does nothing.  The handle must not be in
+ * use by another thread or have work pending on a stream the caller will
+ * not synchronise. */
 admm_status admm_graph_destroy(admm_graph* g);
 
 /* ------------------------------------------------------------------------

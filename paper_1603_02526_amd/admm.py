@@ -23,8 +23,8 @@ STATUS_NAMES = {0: "OK", 1: "E_ARG", 2: "E_STATE", 3: "E_NUMERIC", 4: "E_HIP",
 KIND = dict(nonoverlap=1, wall=2, radius=3, quad=4, box=5, hinge=6, l2=7,
             lindyn=8, lindyn0=9, minerr=10, equal=11, margin=12)
 FP32, FP64 = 0, 1
-OPT_PAIR_ROWS, OPT_DRIVER, OPT_PAIR_STATE = 1, 2, 3
-DRIVER_AUTO, DRIVER_LAUNCHES, DRIVER_RESIDENT = 0, 1, 2
+OPT_PAIR_ROWS, OPT_DRIVER, OPT_PAIR_STATE, OPT_GRAPH_BLOCK = 1, 2, 3, 4
+DRIVER_AUTO, DRIVER_LAUNCHES, DRIVER_RESIDENT, DRIVER_GRAPH = 0, 1, 2, 3
 PAIR_STATE_AUTO, PAIR_STATE_DENSE = 0, 1
 
 
@@ -225,7 +225,7 @@ class Graph:
     def from_problem(cls, problem, precision: int = FP32, device: Optional[int] = 0,
                      rho: Optional[float] = None, alpha: Optional[float] = None,
                      pair_rows: int = 0, driver: int = DRIVER_AUTO,
-                     pair_state: int = PAIR_STATE_AUTO):
+                     pair_state: int = PAIR_STATE_AUTO, graph_block: int = 0):
         """Build from an object with var_dims, groups (kind, var_ids, params,
         shared), rho, alpha and z0.  device=None skips finalize."""
         g = cls(problem.var_dims, precision)
@@ -243,6 +243,8 @@ class Graph:
             g.set_option(OPT_DRIVER, driver)
         if pair_state != PAIR_STATE_AUTO:
             g.set_option(OPT_PAIR_STATE, pair_state)
+        if graph_block:
+            g.set_option(OPT_GRAPH_BLOCK, graph_block)
         if device is not None:
             g.finalize(device)
             g.set_state(problem.z0)

@@ -25,11 +25,30 @@
 #include <numeric>
 #include <vector>
 
-#include <hip/hip_ext.h>
-
-#include "graph_kernels.h"
+#include "graph_plan.h"
 
 using namespace admmg;
+
+namespace admmg {
+
+int64_t zpass_blocks(const Plan& P) {
+  return (int64_t)P.var_b.size() + ((int64_t)P.var_w.size() + ZPB - 1) / ZPB +
+         ((int64_t)P.var_l.size() + NT - 1) / NT;
+}
+
+// Bytes of the resident driver's LDS image: every region rounded up to 16 B,
+// in the order resident_layout assigns them.
+int64_t resident_image_bytes(const Plan& P, int64_t nz, int64_t es) {
+  auto r16 = [](int64_t b) { return (b + 15) / 16 * 16; };
+  int64_t b = r16((P.zc_span + 2 * P.n_m) * es) + 2 * r16(nz * es) + r16((int64_t)P.par.size() * es) +
+              r16((int64_t)P.idx.size() * 4);
+  b += r16((int64_t)P.var_b.size() * 4) + r16((int64_t)P.rng_b.size() * 8) + r16((int64_t)P.deg_b.size() * es);
+  b += r16((int64_t)P.var_w.size() * 4) + r16((int64_t)P.rng_w.size() * 8) + r16((int64_t)P.deg_w.size() * es);
+  b += r16((int64_t)P.var_l.size() * 4) + r16((int64_t)P.deg_l.size() * es);
+  return b;
+}
+
+}  // namespace admmg
 
 namespace {
 
@@ -45,50 +64,6 @@ struct Group {
   }
 };
 
-// Host layout of a finalized graph (precision independent).
-struct Plan {
-  std::vector<BucketDesc> bt;
-  std::vector<int32_t> idx;
-  std::vector<double> par;
-  int64_t n_zc = 0, n_m = 0;    // contribution buffer and m-region element counts
-  int64_t zc_span = 0;          // contribution region incl. padding, rounded up to 64
-  int64_t w_stride = 0;         // medium z lists: fixed stride (0: explicit ranges)
-  int64_t w_base = 0, l_base = 0;  // medium / short z lists: first pool position
-  std::vector<int32_t> var_b, var_w, var_l;   // z lists: long, medium, short
-  std::vector<int64_t> rng_b, rng_w;
-  std::vector<double> deg_b, deg_w, deg_l;  // per z list: sum of its edges' rho / graph rho
-  bool weighted = false;        // groups with different rho: weighted z-sums
-  std::vector<double> wz;       // weighted: relative rho of every contribution position
-  std::vector<double> rmz;      // weighted: per z scalar, the largest rho of its edges
-  bool alpha_one = true;        // every edge has alpha = 1 (m-only state)
-  std::vector<double> ualpha;   // groups with different alpha: alpha per user slot
-  std::vector<int64_t> upos;    // user slot -> pool position of m
-  std::vector<int32_t> uz;      // user slot -> z index
-  int64_t xblocks = 0;
-  int64_t algo_bytes = 0, layout_bytes = 0;  // per iteration, in T units x sizeof later
-  int64_t algo_elems = 0, layout_idx_bytes = 0, layout_elems = 0;
-  int64_t n_pair_tiles = 0;
-  int64_t n_flags = 0;          // sparse pair-state flag words (NT per tile)
-  bool no_tiles = false;        // input: build no dense pair tiles
-  bool resident = false;        // output of finalize: resident driver chosen
-};
-
-struct EngineBase {
-  virtual ~EngineBase() {}
-  // Whether the resident driver can run this plan on the device (LDS image
-  // plus the kernel's static LDS within the per-workgroup limit).
-  virtual admm_status resident_check(const Plan& p, int64_t nz, bool alpha1) = 0;
-  virtual admm_status upload(const Plan& p, const std::vector<double>& z0, double rho,
-                             double alpha) = 0;
-  virtual admm_status set_state(const double* z, const double* u, hipStream_t s) = 0;
-  virtual admm_status run(int32_t iters, hipStream_t s) = 0;
-  virtual admm_status run_profiled(int32_t iters, hipStream_t s, double* x_ms, double* z_ms) = 0;
-  virtual admm_status get_z(double* z, hipStream_t s) = 0;
-  virtual admm_status get_slots(double* out, int which, hipStream_t s) = 0;
-  virtual admm_status residuals(double* r, double* s, hipStream_t st) = 0;
-  virtual void* z_ptr() = 0;
-};
-
 }  // namespace
 
 struct admm_graph {
@@ -100,6 +75,7 @@ struct admm_graph {
   double rho = 1.0, alpha = 1.0;
   int32_t pair_rows = 0;  // rows per dense pair tile (0: chosen at finalize)
   int32_t driver = ADMM_DRIVER_AUTO;
+  int32_t graph_block = 32;  // iterations per recorded block of the graph driver
   int32_t pair_state = ADMM_PAIR_STATE_AUTO;
   int64_t n_factors = 0, n_edges = 0, n_slots = 0;
   int state = 0;  // 0 building, 1 validated (no device), 2 ready
@@ -266,6 +242,12 @@ bool detect_complete_pairs(const admm_graph& g, const Group& gr, std::vector<int
   return true;
 }
 
+// Hinge and margin factors take up to NT - 1 weight components: one
+// register per component up to 64 (dmax 32 or 64), two sweeps over memory
+// above that (dmax 0).
+constexpr int HINGE_DMAX = NT - 1;
+int hinge_dmax(int d) { return d <= 32 ? 32 : d <= 64 ? 64 : 0; }
+
 bool hinge_uniform(const Group& gr) {
   for (int64_t f = 1; f < gr.n; ++f)
     for (int e = 0; e < gr.arity; ++e)
@@ -419,11 +401,11 @@ admm_status build_plan(admm_graph& g, Plan& P, bool no_tiles) {
       }
       P.algo_elems += 2 * (int64_t)gr.n * 6;
 
-    } else if (gr.kind == KD_HINGE && gr.arity - 1 <= 64 && hinge_uniform(gr)) {
+    } else if (gr.kind == KD_HINGE && gr.arity - 1 <= HINGE_DMAX && hinge_uniform(gr)) {
       // ---------------- hinge, shared variable list ----------------
       b.mode = BM_UNIF_HINGE;
       b.d = gr.arity - 1;
-      b.dmax = b.d <= 32 ? 32 : 64;
+      b.dmax = hinge_dmax(b.d);
       b.n = gr.n;
       b.nfp = round_up(gr.n, 64);
       b.nslot = gr.arity;
@@ -498,8 +480,9 @@ admm_status build_plan(admm_graph& g, Plan& P, bool no_tiles) {
       b.nfp = round_up(gr.n, 64);
       const int d = g.dim[gr.vids[0]];
       b.d = d;
-      if (d > 64) return admmi::set_err(ADMM_E_UNSUPPORTED, "MARGIN with d > 64 is not supported");
-      b.dmax = d <= 32 ? 32 : 64;
+      if (d > HINGE_DMAX)
+        return admmi::set_err(ADMM_E_UNSUPPORTED, "MARGIN with d > %d is not supported", HINGE_DMAX);
+      b.dmax = hinge_dmax(d);
       b.nslot = d + 2;
       const int64_t i0 = (int64_t)P.idx.size();
       P.idx.resize(i0 + (int64_t)(d + 2) * b.nfp, 0);
@@ -595,8 +578,9 @@ admm_status build_plan(admm_graph& g, Plan& P, bool no_tiles) {
       b.nslot = fslots(0);
       if (gr.kind == KD_HINGE) {
         b.d = gr.arity - 1;
-        if (b.d > 64) return admmi::set_err(ADMM_E_UNSUPPORTED, "HINGE with d > 64 is not supported");
-        b.dmax = b.d <= 32 ? 32 : 64;
+        if (b.d > HINGE_DMAX)
+          return admmi::set_err(ADMM_E_UNSUPPORTED, "HINGE with d > %d is not supported", HINGE_DMAX);
+        b.dmax = hinge_dmax(b.d);
       }
       if (gr.kind == KD_LINDYN || gr.kind == KD_LINDYN0) {
         b.nn = nn;
@@ -796,477 +780,9 @@ admm_status build_plan(admm_graph& g, Plan& P, bool no_tiles) {
   return ADMM_OK;
 }
 
-int64_t zpass_blocks(const Plan& P) {
-  return (int64_t)P.var_b.size() + ((int64_t)P.var_w.size() + ZPB - 1) / ZPB +
-         ((int64_t)P.var_l.size() + NT - 1) / NT;
-}
-
-// Bytes of the resident driver's LDS image: every region rounded up to 16 B,
-// in the order resident_layout assigns them.
-int64_t resident_image_bytes(const Plan& P, int64_t nz, int64_t es) {
-  auto r16 = [](int64_t b) { return (b + 15) / 16 * 16; };
-  int64_t b = r16((P.zc_span + 2 * P.n_m) * es) + 2 * r16(nz * es) + r16((int64_t)P.par.size() * es) +
-              r16((int64_t)P.idx.size() * 4);
-  b += r16((int64_t)P.var_b.size() * 4) + r16((int64_t)P.rng_b.size() * 8) + r16((int64_t)P.deg_b.size() * es);
-  b += r16((int64_t)P.var_w.size() * 4) + r16((int64_t)P.rng_w.size() * 8) + r16((int64_t)P.deg_w.size() * es);
-  b += r16((int64_t)P.var_l.size() * 4) + r16((int64_t)P.deg_l.size() * es);
-  return b;
-}
-
 constexpr int64_t RES_LDS_BYTES = 96 * 1024;   // image limit of the resident driver
+constexpr int32_t DEFAULT_GRAPH_BLOCK = 32;     // iterations per block of the graph driver
 constexpr int64_t RES_AUTO_MAX_BLOCKS = 64;    // auto: resident up to this many pass blocks
-
-// ---------------------------------------------------------------------------
-// Device engine for one working precision.
-// ---------------------------------------------------------------------------
-template <typename T>
-struct Engine : EngineBase {
-  int device = 0;
-  bool alpha1 = true;
-  T alpha = T(1), inv_rho = T(1);
-  int nb = 0;
-  int fs = FS_ALL;  // x-pass feature set
-  int64_t xblocks = 0, zblocks = 0, nb_w = 0, n_w = 0, n_l = 0, n_slots = 0, nz = 0, xdelta = 0;
-  int64_t n_b = 0;
-  int64_t w_stride = 0, w_base = 0, l_base = 0;
-  int32_t *var_b = nullptr;
-  int64_t* rng_b = nullptr;
-  T* deg_b = nullptr;
-  bool resident = false;
-  uint16_t* flags = nullptr;
-  int64_t n_flags = 0;
-  ResArgs<T> ra{};
-  size_t res_lds = 0;
-  T* pool = nullptr;
-  T* par = nullptr;
-  int32_t* idx = nullptr;
-  BucketDesc* bt = nullptr;
-  T* z[2] = {nullptr, nullptr};
-  int zc = 0;
-  int32_t *var_w = nullptr, *var_l = nullptr;
-  int64_t* rng_w = nullptr;
-  T *deg_w = nullptr, *deg_l = nullptr;
-  int64_t* upos = nullptr;
-  int32_t* uz = nullptr;
-  T *bmx = nullptr, *bmz = nullptr;
-  bool weighted = false;           // groups with different rho
-  T* ualpha = nullptr;             // groups with different alpha: alpha per user slot
-  T *wz = nullptr, *rmz = nullptr;  // weighted: rho per contribution position, largest rho per z
-  double* io = nullptr;
-  int64_t io_n = 0;
-  bool have_resid = false;
-  std::vector<void*> allocs;
-
-  ~Engine() override {
-    if (!allocs.empty()) {
-      hipSetDevice(device);
-      for (void* p : allocs) hipFree(p);
-    }
-  }
-
-  template <typename U>
-  admm_status alloc(U** p, int64_t n) {
-    *p = nullptr;
-    const size_t bytes = (size_t)std::max<int64_t>(n, 1) * sizeof(U);
-    ADMM_HIP(hipMalloc((void**)p, bytes));
-    allocs.push_back(*p);
-    return ADMM_OK;
-  }
-
-  template <typename U>
-  admm_status put(U** p, const std::vector<U>& v) {
-    admm_status s = alloc(p, (int64_t)v.size());
-    if (s) return s;
-    if (!v.empty()) ADMM_HIP(hipMemcpy(*p, v.data(), v.size() * sizeof(U), hipMemcpyHostToDevice));
-    return ADMM_OK;
-  }
-
-  admm_status put_conv(T** p, const std::vector<double>& v) {
-    std::vector<T> t(v.begin(), v.end());
-    return put(p, t);
-  }
-
-  template <bool A1>
-  static const void* resident_fn() {
-    return reinterpret_cast<const void*>(&resident_kernel<T, A1>);
-  }
-
-  admm_status resident_check(const Plan& P, int64_t nz_, bool a1) override {
-    const int64_t bytes = resident_image_bytes(P, nz_, (int64_t)sizeof(T));
-    hipFuncAttributes fa;
-    ADMM_HIP(hipFuncGetAttributes(&fa, a1 ? resident_fn<true>() : resident_fn<false>()));
-    int maxsh = 0;
-    ADMM_HIP(hipDeviceGetAttribute(&maxsh, hipDeviceAttributeMaxSharedMemoryPerBlock, device));
-    if ((int64_t)fa.sharedSizeBytes + bytes > (int64_t)maxsh)
-      return admmi::set_err(ADMM_E_UNSUPPORTED,
-                            "resident driver: LDS image %lld B + static %zu B exceeds %d B",
-                            (long long)bytes, (size_t)fa.sharedSizeBytes, maxsh);
-    if (bytes > 64 * 1024) {
-      ADMM_HIP(hipFuncSetAttribute(a1 ? resident_fn<true>() : resident_fn<false>(),
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
-    }
-    return ADMM_OK;
-  }
-
-  // Region table and LDS offsets of the resident driver (same order and
-  // rounding as resident_image_bytes).
-  void resident_layout() {
-    ResArgs<T>& r = ra;
-    r = ResArgs<T>{};
-    int32_t off = 0;
-    auto add = [&](const void* src, void* back, int64_t bytes) {
-      const int32_t o = off;
-      if (bytes > 0) {
-        ResRegion& q = r.reg[r.nreg++];
-        q.src = src;
-        q.back = back;
-        q.off = o;
-        q.words = (int32_t)(bytes / 4);
-      }
-      off += (int32_t)((bytes + 15) / 16 * 16);
-      return o;
-    };
-    const int64_t es = (int64_t)sizeof(T);
-    r.o_pool = add(pool, pool, pool_n * es);
-    r.o_z0 = add(z[0], nullptr, nz * es);
-    r.o_z1 = add(z[1], nullptr, nz * es);
-    r.o_par = add(par, nullptr, par_n * es);
-    r.o_idx = add(idx, nullptr, idx_n * 4);
-    r.o_var_b = add(var_b, nullptr, n_b * 4);
-    r.o_rng_b = add(rng_b, nullptr, n_b * 16);
-    r.o_deg_b = add(deg_b, nullptr, n_b * es);
-    r.o_var_w = add(var_w, nullptr, n_w * 4);
-    r.o_rng_w = add(rng_w, nullptr, w_stride ? 0 : n_w * 16);
-    r.o_deg_w = add(deg_w, nullptr, n_w * es);
-    r.o_var_l = add(var_l, nullptr, n_l * 4);
-    r.o_deg_l = add(deg_l, nullptr, n_l * es);
-    r.xblocks = (int32_t)xblocks;
-    r.zblocks = (int32_t)zblocks;
-    r.z_words = (int32_t)(nz * es / 4);
-    r.z_back[0] = z[0];
-    r.z_back[1] = z[1];
-    res_lds = (size_t)off;
-  }
-
-  int64_t pool_n = 0, par_n = 0, idx_n = 0;
-
-  admm_status upload(const Plan& P, const std::vector<double>& z0, double rho,
-                     double alpha_) override {
-    alpha1 = P.alpha_one;
-    (void)alpha_;
-    alpha = (T)alpha_;
-    inv_rho = (T)(1.0 / rho);
-    nb = (int)P.bt.size();
-    xblocks = P.xblocks;
-    {
-      int need = 0;
-      for (const BucketDesc& b : P.bt) {
-        if (b.mode == BM_PAIR) need |= b.sparse ? FT_PAIRSP : FT_PAIR;
-        else if (b.mode == BM_UNIF_HINGE && b.dmax <= 32) need |= FT_UHINGE;
-        else if (b.mode == BM_GEN_SLOT || b.kind == KD_NONOVERLAP || b.kind == KD_WALL ||
-                 b.kind == KD_EQUAL)
-          need |= FT_GEN;
-        else need |= FT_WIDE;
-      }
-      fs = ((need & ~FS_PAIR) == 0)     ? FS_PAIR
-           : ((need & ~FS_PAIRSP) == 0) ? FS_PAIRSP
-           : ((need & ~FS_HINGE) == 0)  ? FS_HINGE
-                                        : FS_ALL;
-    }
-    n_b = (int64_t)P.var_b.size();
-    w_stride = P.w_stride;
-    w_base = P.w_base;
-    l_base = P.l_base;
-    n_w = (int64_t)P.var_w.size();
-    n_l = (int64_t)P.var_l.size();
-    nb_w = (n_w + ZPB - 1) / ZPB;
-    zblocks = zpass_blocks(P);
-    resident = P.resident;
-    n_slots = (int64_t)P.upos.size();
-    nz = (int64_t)z0.size();
-    xdelta = P.n_m;
-    admm_status s;
-    pool_n = P.zc_span + 2 * P.n_m;
-    par_n = (int64_t)P.par.size();
-    idx_n = (int64_t)P.idx.size();
-    if ((s = alloc(&pool, pool_n))) return s;
-    ADMM_HIP(hipMemset(pool, 0, (size_t)std::max<int64_t>(pool_n, 1) * sizeof(T)));
-    if ((s = put_conv(&par, P.par))) return s;
-    if ((s = put(&idx, P.idx))) return s;
-    if ((s = put(&bt, P.bt))) return s;
-    if ((s = alloc(&z[0], nz))) return s;
-    if ((s = alloc(&z[1], nz))) return s;
-    if ((s = put(&var_b, P.var_b))) return s;
-    if ((s = put(&rng_b, P.rng_b))) return s;
-    if ((s = put_conv(&deg_b, P.deg_b))) return s;
-    if ((s = put(&var_w, P.var_w))) return s;
-    if ((s = put(&var_l, P.var_l))) return s;
-    if ((s = put(&rng_w, P.rng_w))) return s;
-    if ((s = put_conv(&deg_w, P.deg_w))) return s;
-    if ((s = put_conv(&deg_l, P.deg_l))) return s;
-    if ((s = put(&upos, P.upos))) return s;
-    if ((s = put(&uz, P.uz))) return s;
-    if (!P.ualpha.empty())
-      if ((s = put_conv(&ualpha, P.ualpha))) return s;
-    weighted = P.weighted;
-    if (weighted) {
-      if ((s = put_conv(&wz, P.wz))) return s;
-      if ((s = put_conv(&rmz, P.rmz))) return s;
-    }
-    if ((s = alloc(&bmx, xblocks))) return s;
-    if ((s = alloc(&bmz, zblocks))) return s;
-    io_n = std::max(n_slots, nz);
-    if ((s = alloc(&io, io_n))) return s;
-    n_flags = P.n_flags;
-    if ((s = alloc(&flags, n_flags))) return s;
-    if (resident) resident_layout();
-    return set_state(z0.data(), nullptr, nullptr);
-  }
-
-  admm_status set_state(const double* zh, const double* uh, hipStream_t st) override {
-    ADMM_HIP(hipSetDevice(device));
-    ADMM_HIP(hipMemcpyAsync(io, zh, nz * sizeof(double), hipMemcpyHostToDevice, st));
-    const int64_t gz = (nz + 255) / 256;
-    if (gz) convert_kernel<T><<<gz, 256, 0, st>>>(nz, io, z[zc]);
-    ADMM_HIP(hipGetLastError());
-    if (uh) {
-      ADMM_HIP(hipMemcpyAsync(io, uh, n_slots * sizeof(double), hipMemcpyHostToDevice, st));
-    }
-    const int64_t gs = (n_slots + 255) / 256;
-    if (gs)
-      set_state_kernel<T><<<gs, 256, 0, st>>>(n_slots, upos, uz, uh ? io : nullptr, z[zc], pool,
-                                              xdelta, 1);
-    // every pair's m is explicit in the dense arrays after a state import
-    if (n_flags)
-      fill_u16_kernel<<<(unsigned)((n_flags + 255) / 256), 256, 0, st>>>(n_flags, 0xFFFF, flags);
-    ADMM_HIP(hipGetLastError());
-    ADMM_HIP(hipStreamSynchronize(st));
-    have_resid = false;
-    return ADMM_OK;
-  }
-
-  XArgs<T> xargs() const {
-    XArgs<T> a;
-    a.pool = pool;
-    a.idx = idx;
-    a.par = par;
-    a.z = z[zc];
-    a.zprev = z[zc ^ 1];
-    a.flags = flags;
-    a.blockmax = bmx;
-    a.bt = bt;
-    a.nb = nb;
-    a.alpha = alpha;
-    a.inv_rho = inv_rho;
-    return a;
-  }
-
-  // Launches take an optional start/stop event pair recorded at the
-  // kernel's own begin and end (hipExtLaunchKernelGGL), used for timing.
-  template <bool A1, int FS>
-  void launch_x_fs(int mode, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
-    XArgs<T> a = xargs();
-    const dim3 g((unsigned)xblocks), b(NT);
-    if (mode == PM_NORMAL)
-      hipExtLaunchKernelGGL((xpass_kernel<T, A1, PM_NORMAL, FS>), g, b, 0, st, e0, e1, 0, a);
-    else if (mode == PM_SAVE)
-      hipExtLaunchKernelGGL((xpass_kernel<T, A1, PM_SAVE, FS>), g, b, 0, st, e0, e1, 0, a);
-    else
-      hipExtLaunchKernelGGL((xpass_kernel<T, A1, PM_RESID, FS>), g, b, 0, st, e0, e1, 0, a);
-  }
-
-  template <bool A1>
-  void launch_x(int mode, hipStream_t st, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
-    if (fs == FS_PAIR) launch_x_fs<A1, FS_PAIR>(mode, st, e0, e1);
-    else if (fs == FS_PAIRSP) launch_x_fs<A1, FS_PAIRSP>(mode, st, e0, e1);
-    else if (fs == FS_HINGE) launch_x_fs<A1, FS_HINGE>(mode, st, e0, e1);
-    else launch_x_fs<A1, FS_ALL>(mode, st, e0, e1);
-  }
-
-  ZArgs<T> zargs(int check) const {
-    ZArgs<T> a;
-    a.pool = pool;
-    a.var_b = var_b;
-    a.rng_b = rng_b;
-    a.deg_b = deg_b;
-    a.n_b = (int32_t)n_b;
-    a.var_w = var_w;
-    a.rng_w = rng_w;
-    a.deg_w = deg_w;
-    a.n_w = n_w;
-    a.nb_w = (int32_t)nb_w;
-    a.var_l = var_l;
-    a.deg_l = deg_l;
-    a.n_l = n_l;
-    a.w_stride = w_stride;
-    a.w_base = w_base;
-    a.l_base = l_base;
-    a.wz = wz;
-    a.rmz = rmz;
-    a.zin = z[zc];
-    a.zout = z[zc ^ 1];
-    a.blockmax = bmz;
-    a.check = check;
-    return a;
-  }
-
-  void launch_z(int check, hipStream_t st, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
-    ZArgs<T> a = zargs(check);
-    if (zblocks)
-      hipExtLaunchKernelGGL((zpass_kernel<T>), dim3((unsigned)zblocks), dim3(NT), 0, st, e0, e1, 0, a);
-    zc ^= 1;
-  }
-
-  // The whole run in one launch of one workgroup (resident driver).
-  void launch_resident(int32_t iters, hipStream_t st, hipEvent_t e0 = nullptr,
-                       hipEvent_t e1 = nullptr) {
-    ResArgs<T> r = ra;
-    r.zc = zc;
-    r.iters = iters;
-    const XArgs<T> xa = xargs();
-    const ZArgs<T> za = zargs(0);
-    if (alpha1)
-      hipExtLaunchKernelGGL((resident_kernel<T, true>), dim3(1), dim3(NT), res_lds, st, e0, e1, 0,
-                            xa, za, r);
-    else
-      hipExtLaunchKernelGGL((resident_kernel<T, false>), dim3(1), dim3(NT), res_lds, st, e0, e1, 0,
-                            xa, za, r);
-    if (iters & 1) zc ^= 1;
-  }
-
-  admm_status run(int32_t iters, hipStream_t st) override {
-    if (iters <= 0) return ADMM_OK;
-    ADMM_HIP(hipSetDevice(device));
-    if (resident) {
-      launch_resident(iters, st);
-      ADMM_HIP(hipGetLastError());
-      have_resid = true;
-      return ADMM_OK;
-    }
-    for (int32_t k = 0; k < iters; ++k) {
-      const bool last = (k == iters - 1);
-      if (xblocks) {
-        if (alpha1) launch_x<true>(last ? PM_SAVE : PM_NORMAL, st);
-        else launch_x<false>(PM_NORMAL, st);
-      }
-      launch_z(last ? 1 : 0, st);
-    }
-    if (xblocks) {
-      if (alpha1) launch_x<true>(PM_RESID, st);
-      else launch_x<false>(PM_RESID, st);
-    }
-    ADMM_HIP(hipGetLastError());
-    have_resid = true;
-    return ADMM_OK;
-  }
-
-  // Same launches as run(), with an event pair around every kernel; returns
-  // the summed x-pass and z-pass durations in milliseconds (synchronises).
-  admm_status run_profiled(int32_t iters, hipStream_t st, double* x_ms, double* z_ms) override {
-    *x_ms = 0.0;
-    *z_ms = 0.0;
-    if (iters <= 0) return ADMM_OK;
-    ADMM_HIP(hipSetDevice(device));
-    if (resident) {
-      hipEvent_t e0, e1;
-      ADMM_HIP(hipEventCreate(&e0));
-      ADMM_HIP(hipEventCreate(&e1));
-      launch_resident(iters, st, e0, e1);
-      hipError_t e = hipGetLastError();
-      if (e == hipSuccess) e = hipStreamSynchronize(st);
-      float ms = 0.f;
-      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-      hipEventDestroy(e0);
-      hipEventDestroy(e1);
-      if (e != hipSuccess) return admmi::set_err(ADMM_E_HIP, "profiled run: %s", hipGetErrorString(e));
-      *x_ms = ms;
-      have_resid = true;
-      return ADMM_OK;
-    }
-    std::vector<hipEvent_t> ev(4 * (size_t)iters);
-    for (auto& e : ev) ADMM_HIP(hipEventCreate(&e));
-    admm_status rc = ADMM_OK;
-    for (int32_t k = 0; k < iters; ++k) {
-      const bool last = (k == iters - 1);
-      if (xblocks) {
-        if (alpha1) launch_x<true>(last ? PM_SAVE : PM_NORMAL, st, ev[4 * k + 0], ev[4 * k + 1]);
-        else launch_x<false>(PM_NORMAL, st, ev[4 * k + 0], ev[4 * k + 1]);
-      } else {
-        hipEventRecord(ev[4 * k + 0], st);
-        hipEventRecord(ev[4 * k + 1], st);
-      }
-      if (zblocks) {
-        launch_z(last ? 1 : 0, st, ev[4 * k + 2], ev[4 * k + 3]);
-      } else {
-        hipEventRecord(ev[4 * k + 2], st);
-        launch_z(last ? 1 : 0, st);
-        hipEventRecord(ev[4 * k + 3], st);
-      }
-    }
-    if (xblocks) {
-      if (alpha1) launch_x<true>(PM_RESID, st);
-      else launch_x<false>(PM_RESID, st);
-    }
-    hipError_t e = hipGetLastError();
-    if (e == hipSuccess) e = hipStreamSynchronize(st);
-    if (e != hipSuccess) rc = admmi::set_err(ADMM_E_HIP, "profiled run: %s", hipGetErrorString(e));
-    for (int32_t k = 0; rc == ADMM_OK && k < iters; ++k) {
-      float a = 0.f, b = 0.f;
-      hipEventElapsedTime(&a, ev[4 * k + 0], ev[4 * k + 1]);
-      hipEventElapsedTime(&b, ev[4 * k + 2], ev[4 * k + 3]);
-      *x_ms += a;
-      *z_ms += b;
-    }
-    for (auto& ee : ev) hipEventDestroy(ee);
-    have_resid = (rc == ADMM_OK);
-    return rc;
-  }
-
-  admm_status get_z(double* out, hipStream_t st) override {
-    ADMM_HIP(hipSetDevice(device));
-    const int64_t g = (nz + 255) / 256;
-    if (g) widen_kernel<T><<<g, 256, 0, st>>>(nz, z[zc], io);
-    ADMM_HIP(hipGetLastError());
-    ADMM_HIP(hipMemcpyAsync(out, io, nz * sizeof(double), hipMemcpyDeviceToHost, st));
-    ADMM_HIP(hipStreamSynchronize(st));
-    return ADMM_OK;
-  }
-
-  admm_status get_slots(double* out, int which, hipStream_t st) override {
-    ADMM_HIP(hipSetDevice(device));
-    const int64_t g = (n_slots + 255) / 256;
-    if (g) {
-      if (alpha1)
-        get_slots_kernel<T, true><<<g, 256, 0, st>>>(n_slots, upos, uz, pool, z[zc], xdelta, alpha,
-                                                      nullptr, which, io);
-      else
-        get_slots_kernel<T, false><<<g, 256, 0, st>>>(n_slots, upos, uz, pool, z[zc], xdelta,
-                                                       alpha, ualpha, which, io);
-    }
-    ADMM_HIP(hipGetLastError());
-    ADMM_HIP(hipMemcpyAsync(out, io, n_slots * sizeof(double), hipMemcpyDeviceToHost, st));
-    ADMM_HIP(hipStreamSynchronize(st));
-    return ADMM_OK;
-  }
-
-  admm_status residuals(double* r, double* s, hipStream_t st) override {
-    if (!have_resid) return admmi::set_err(ADMM_E_STATE, "no iteration has been run since the last state change");
-    ADMM_HIP(hipSetDevice(device));
-    std::vector<T> hx(std::max<int64_t>(xblocks, 1), T(0)), hz(std::max<int64_t>(zblocks, 1), T(0));
-    if (xblocks) ADMM_HIP(hipMemcpyAsync(hx.data(), bmx, xblocks * sizeof(T), hipMemcpyDeviceToHost, st));
-    if (zblocks) ADMM_HIP(hipMemcpyAsync(hz.data(), bmz, zblocks * sizeof(T), hipMemcpyDeviceToHost, st));
-    ADMM_HIP(hipStreamSynchronize(st));
-    T a = T(0), b = T(0);
-    for (T v : hx) a = std::max(a, v);
-    for (T v : hz) b = std::max(b, v);
-    *r = (double)a;
-    // weighted graphs scale each variable's change by its largest rho in the kernel
-    *s = weighted ? (double)b : (double)b / (double)inv_rho;
-    return ADMM_OK;
-  }
-
-  void* z_ptr() override { return z[zc]; }
-};
 
 admm_status check_graph(admm_graph* g) {
   if (!g) return admmi::set_err(ADMM_E_ARG, "graph handle is NULL");
@@ -1407,9 +923,16 @@ admm_status admm_graph_set_option(admm_graph* g, int32_t option, int64_t value) 
       g->pair_state = (int32_t)value;
       return ADMM_OK;
     case ADMM_OPT_DRIVER:
-      if (value != ADMM_DRIVER_AUTO && value != ADMM_DRIVER_LAUNCHES && value != ADMM_DRIVER_RESIDENT)
-        return admmi::set_err(ADMM_E_ARG, "driver must be 0 (auto), 1 (launches) or 2 (resident)");
+      if (value != ADMM_DRIVER_AUTO && value != ADMM_DRIVER_LAUNCHES &&
+          value != ADMM_DRIVER_RESIDENT && value != ADMM_DRIVER_GRAPH)
+        return admmi::set_err(ADMM_E_ARG,
+                              "driver must be 0 (auto), 1 (launches), 2 (resident) or 3 (graph)");
       g->driver = (int32_t)value;
+      return ADMM_OK;
+    case ADMM_OPT_GRAPH_BLOCK:
+      if (value != 0 && (value < 2 || value > 4096 || (value & 1)))
+        return admmi::set_err(ADMM_E_ARG, "graph block must be 0 (default) or even in [2, 4096]");
+      g->graph_block = value ? (int32_t)value : DEFAULT_GRAPH_BLOCK;
       return ADMM_OK;
     default:
       return admmi::set_err(ADMM_E_ARG, "unknown option %d", option);
@@ -1422,7 +945,8 @@ admm_status admm_graph_finalize(admm_graph* g, int32_t device) {
   if (g->state == 2) return admmi::set_err(ADMM_E_STATE, "graph already finalized");
   const int64_t es_ = g->precision == ADMM_FP64 ? 8 : 4;
   // Resident candidates: the m and x regions alone must fit the LDS image.
-  bool want_res = g->driver != ADMM_DRIVER_LAUNCHES && g->n_slots * 2 * es_ <= RES_LDS_BYTES;
+  bool want_res = (g->driver == ADMM_DRIVER_AUTO || g->driver == ADMM_DRIVER_RESIDENT) &&
+                  g->n_slots * 2 * es_ <= RES_LDS_BYTES;
   if (g->driver == ADMM_DRIVER_RESIDENT && !want_res)
     return admmi::set_err(ADMM_E_UNSUPPORTED, "resident driver: %lld slots do not fit in LDS",
                           (long long)g->n_slots);
@@ -1458,7 +982,10 @@ admm_status admm_graph_finalize(admm_graph* g, int32_t device) {
   // per-factor prox data; layout: indices, partial sums and their reads.
   I.algo_bytes_per_iter = P.algo_elems * es * (P.alpha_one ? 1 : 2);
   I.layout_bytes_per_iter = P.layout_elems * es + P.layout_idx_bytes;
-  I.driver = P.resident ? ADMM_DRIVER_RESIDENT : ADMM_DRIVER_LAUNCHES;
+  // without the resident driver: launches when asked for, else recorded
+  // iteration blocks (the same kernels in the same order)
+  const int32_t eager = g->driver == ADMM_DRIVER_LAUNCHES ? ADMM_DRIVER_LAUNCHES : ADMM_DRIVER_GRAPH;
+  I.driver = P.resident ? ADMM_DRIVER_RESIDENT : eager;
   I.sparse_pair_state = P.n_flags > 0 ? 1 : 0;
   I.resident_lds_bytes = P.resident ? (int32_t)resident_image_bytes(P, g->nz, es) : 0;
   if (admm_status s = admmi::probe_device(device)) {
@@ -1466,25 +993,18 @@ admm_status admm_graph_finalize(admm_graph* g, int32_t device) {
     return s;
   }
   ADMM_HIP(hipSetDevice(device));
-  std::unique_ptr<EngineBase> eng;
-  if (g->precision == ADMM_FP64) {
-    auto* e = new Engine<double>();
-    e->device = device;
-    eng.reset(e);
-  } else {
-    auto* e = new Engine<float>();
-    e->device = device;
-    eng.reset(e);
-  }
+  std::unique_ptr<EngineBase> eng(g->precision == ADMM_FP64 ? make_engine_f64(device)
+                                                              : make_engine_f32(device));
   if (g->plan.resident) {
     if (admm_status s = eng->resident_check(P, g->nz, P.alpha_one)) {
       if (g->driver == ADMM_DRIVER_RESIDENT) return s;
       admmi::clear_err();
       g->plan.resident = false;  // auto: the same plan runs with launches
-      I.driver = ADMM_DRIVER_LAUNCHES;
+      I.driver = eager;
       I.resident_lds_bytes = 0;
     }
   }
+  eng->graph_block = I.driver == ADMM_DRIVER_GRAPH ? g->graph_block : 0;
   std::vector<double> z0(g->nz, 0.0);
   if (admm_status s = eng->upload(P, z0, g->rho, g->alpha)) return s;
   g->eng = std::move(eng);

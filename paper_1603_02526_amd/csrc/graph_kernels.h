@@ -888,6 +888,128 @@ __device__ __forceinline__ void xpass_hinge(const XArgs<T>& a, const BucketDesc&
   }
 }
 
+// Hinge and margin factors with d > 64 weight components (up to NT - 1):
+// the same operator as xpass_hinge without register arrays.  A first sweep
+// over the components forms the dot product s = y(n_w.a + n_b) (+ n_xi);
+// once tau is known a second sweep reads each component's m, z and y a
+// again and writes its outputs, in the same order as xpass_hinge.
+template <typename T, bool A1, int MODE, bool UNIF>
+__device__ __forceinline__ void xpass_hinge_wide(const XArgs<T>& a, const BucketDesc& b,
+                                                 int blk) {
+  __shared__ T wsw[NT / 64][NT];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int d = b.d;
+  const int64_t f = (int64_t)blk * NT + t;
+  const bool valid = f < b.n;
+  const int64_t ff = valid ? f : 0;
+  const int64_t nfp = b.nfp;
+  const int32_t* zo = a.idx + b.idx_off;
+  const T* P = a.par + b.par_off;
+  T* M = a.pool + b.m_off;
+  T* X = a.pool + b.x_off;
+  const T alpha = (T)b.alpha;
+  T dot = T(0), rmax = T(0);
+  for (int k = 0; k < d; ++k) {
+    const T zk = UNIF ? a.z[zo[k]] : a.z[zo[k * nfp + ff]];
+    const T mk = M[k * nfp + ff];
+    T xo = T(0);
+    if constexpr (!A1 || MODE == PM_RESID) xo = X[k * nfp + ff];
+    if constexpr (MODE == PM_RESID) {
+      if (valid) rmax = tmax(rmax, tabs(xo - zk));
+    } else {
+      T uk, nk;
+      state_un<T, A1>(mk, xo, zk, alpha, uk, nk);
+      dot += nk * P[k * nfp + ff];
+    }
+  }
+  const T zb = UNIF ? a.z[zo[d]] : a.z[zo[d * nfp + ff]];
+  const T mb = M[d * nfp + ff];
+  T xob = T(0);
+  if constexpr (!A1 || MODE == PM_RESID) xob = X[d * nfp + ff];
+  const bool margin = !UNIF && b.kind == KD_MARGIN;
+  T zs = T(0), ms = T(0), xos = T(0);
+  if (margin) {
+    zs = a.z[zo[(d + 1) * nfp + ff]];
+    ms = M[(d + 1) * nfp + ff];
+    if constexpr (!A1 || MODE == PM_RESID) xos = X[(d + 1) * nfp + ff];
+  }
+  if constexpr (MODE == PM_RESID) {
+    if (valid) rmax = tmax(rmax, tabs(xob - zb));
+    if (valid && margin) rmax = tmax(rmax, tabs(xos - zs));
+    block_max_store(rmax, a.blockmax);
+    return;
+  } else {
+    T ub, nb;
+    state_un<T, A1>(mb, xob, zb, alpha, ub, nb);
+    const T y = P[d * nfp + ff], C = P[(d + 1) * nfp + ff], iD = P[(d + 2) * nfp + ff];
+    dot += y * nb;
+    T us = T(0), ns = T(0);
+    if (margin) {
+      state_un<T, A1>(ms, xos, zs, alpha, us, ns);
+      dot += ns;
+    }
+    const T tau = tmin(C, tmax(T(0), (T(1) - dot) * iD));
+    const T st = tau * (T)b.irho;
+    const T xb = nb + st * y;
+    const T mnb = xb + ub;
+    const bool shared_b = !UNIF && b.ub;
+    if (valid) {
+      M[d * nfp + ff] = mnb;
+      if constexpr (!A1 || MODE == PM_SAVE) X[d * nfp + ff] = xb;
+      if constexpr (!UNIF) {
+        if (!shared_b) a.pool[a.idx[b.dst_off + d * nfp + ff]] = mnb;
+      }
+      if (margin) {
+        const T xs = ns + st;
+        M[(d + 1) * nfp + ff] = xs + us;
+        if constexpr (!A1 || MODE == PM_SAVE) X[(d + 1) * nfp + ff] = xs;
+        a.pool[a.idx[b.dst_off + (d + 1) * nfp + ff]] = xs + us;
+      }
+    }
+    for (int k = 0; k < d; ++k) {
+      const T zk = UNIF ? a.z[zo[k]] : a.z[zo[k * nfp + ff]];
+      const T mk = M[k * nfp + ff];
+      T xo = T(0);
+      if constexpr (!A1) xo = X[k * nfp + ff];
+      T uk, nk;
+      state_un<T, A1>(mk, xo, zk, alpha, uk, nk);
+      const T xk = nk + st * P[k * nfp + ff];
+      const T mn = xk + uk;
+      if (valid) {
+        M[k * nfp + ff] = mn;
+        if constexpr (!A1 || MODE == PM_SAVE) X[k * nfp + ff] = xk;
+        if constexpr (!UNIF) a.pool[a.idx[b.dst_off + k * nfp + ff]] = mn;
+      }
+      if constexpr (UNIF) {
+        const T s = admmi::wave_sum(valid ? mn : T(0));
+        if (lane == 0) wsw[w][k] = s;
+      }
+    }
+    if (shared_b) {
+      const T sb = admmi::wave_sum(valid ? mnb : T(0));
+      if (lane == 0) wsw[w][0] = sb;
+      __syncthreads();
+      if (t == 0) {
+        T acc = wsw[0][0];
+#pragma unroll
+        for (int q = 1; q < NT / 64; ++q) acc += wsw[q][0];
+        a.pool[a.idx[b.dst_off + d * nfp + blk]] = acc;
+      }
+    }
+    if constexpr (UNIF) {
+      const T s = admmi::wave_sum(valid ? mnb : T(0));
+      if (lane == 0) wsw[w][d] = s;
+      __syncthreads();
+      if (t <= d) {
+        T acc = wsw[0][t];
+#pragma unroll
+        for (int q = 1; q < NT / 64; ++q) acc += wsw[q][t];
+        a.pool[a.idx[b.dst_off + (int64_t)blk * (d + 1) + t]] = acc;
+      }
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Separable operators, one thread per scalar slot.  Params [2][nfp]:
 //   RADIUS  x = max(0, p0 n), p0 = rho/(rho - gamma)
@@ -1140,11 +1262,14 @@ enum Features : int {
   FT_GEN = 4,      // non-overlap/wall on arbitrary variables, separable slots
   FT_WIDE = 8,     // hinge with d <= 64, general hinge, linear dynamics
   FT_PAIRSP = 16,  // dense pair tiles with sparse pair state
+  FT_XWIDE = 32,   // hinge and margin with 64 < d < NT (two sweeps, no register arrays)
 };
 constexpr int FS_PAIR = FT_PAIR | FT_GEN;
 constexpr int FS_PAIRSP = FT_PAIRSP | FT_GEN;
 constexpr int FS_HINGE = FT_UHINGE | FT_GEN;
 constexpr int FS_ALL = FT_PAIR | FT_UHINGE | FT_GEN | FT_WIDE | FT_PAIRSP;
+constexpr int FS_XW = FT_XWIDE | FT_GEN;
+constexpr int FS_ALLX = FS_ALL | FT_XWIDE;
 
 // One x-pass workgroup's work; blk indexes the x-pass blocks of all buckets.
 template <typename T, bool A1, int MODE, int FS>
@@ -1183,18 +1308,22 @@ __device__ __forceinline__ void xpass_block(XArgs<T> a, int blk) {
       else
         xpass_pair<T, A1, MODE, 64>(a, b, local);
     }
-  } else if ((FS & (FT_UHINGE | FT_WIDE)) && b.mode == BM_UNIF_HINGE) {
-    if ((FS & FT_UHINGE) && b.dmax <= 32)
+  } else if ((FS & (FT_UHINGE | FT_WIDE | FT_XWIDE)) && b.mode == BM_UNIF_HINGE) {
+    if ((FS & FT_UHINGE) && b.dmax == 32)
       xpass_hinge<T, A1, MODE, true, 32>(a, b, local);
-    else if (FS & FT_WIDE)
+    else if ((FS & FT_WIDE) && b.dmax == 64)
       xpass_hinge<T, A1, MODE, true, 64>(a, b, local);
+    else if ((FS & FT_XWIDE) && b.dmax == 0)
+      xpass_hinge_wide<T, A1, MODE, true>(a, b, local);
   } else if ((FS & FT_GEN) && b.mode == BM_GEN_SLOT) {
     xpass_slot<T, A1, MODE>(a, b, local);
   } else if ((FS & FT_GEN) && (b.kind == KD_NONOVERLAP || b.kind == KD_WALL || b.kind == KD_EQUAL)) {
     xpass_geom<T, A1, MODE>(a, b, local);
+  } else if ((FS & FT_XWIDE) && (b.kind == KD_HINGE || b.kind == KD_MARGIN) && b.dmax == 0) {
+    xpass_hinge_wide<T, A1, MODE, false>(a, b, local);
   } else if (FS & FT_WIDE) {
     if (b.kind == KD_HINGE || b.kind == KD_MARGIN) {
-      if (b.dmax <= 32)
+      if (b.dmax == 32)
         xpass_hinge<T, A1, MODE, false, 32>(a, b, local);
       else
         xpass_hinge<T, A1, MODE, false, 64>(a, b, local);
@@ -1216,6 +1345,7 @@ __global__ __launch_bounds__(NT) void xpass_kernel(XArgs<T> a) {
 // remaining blocks: one short list per lane, summed in order.
 constexpr int ZSEG = 16;                  // lanes per medium list
 constexpr int ZPB = NT / ZSEG;            // medium lists per block
+constexpr int ZUN = 8;                    // loads per lane issued at once (medium lists)
 template <typename T>
 __device__ __forceinline__ void zpass_block(ZArgs<T> a, int blk) {
   __shared__ T zred[NT / 64];
@@ -1248,13 +1378,22 @@ __device__ __forceinline__ void zpass_block(ZArgs<T> a, int blk) {
     T s = T(0);
     if (ok) {
       if (a.w_stride) {
+        // The first ZUN loads of each lane are issued together before any
+        // sum (the list is a few strides long: one memory round trip instead
+        // of one per stride); the sum order is the same as a sequential loop.
         const int64_t o = a.w_base + k * a.w_stride;
         const T* p = a.pool + o;
-        if (a.wz) {
-          for (int64_t j = sl; j < a.w_stride; j += ZSEG) s += a.wz[o + j] * p[j];
-        } else {
-          for (int64_t j = sl; j < a.w_stride; j += ZSEG) s += p[j];
+        T v[ZUN];
+#pragma unroll
+        for (int q = 0; q < ZUN; ++q) {
+          const int64_t j = sl + q * ZSEG;
+          v[q] = T(0);
+          if (j < a.w_stride) v[q] = a.wz ? a.wz[o + j] * p[j] : p[j];
         }
+#pragma unroll
+        for (int q = 0; q < ZUN; ++q) s += v[q];
+        for (int64_t j = sl + ZUN * ZSEG; j < a.w_stride; j += ZSEG)
+          s += a.wz ? a.wz[o + j] * p[j] : p[j];
       } else {
         const int64_t o1 = a.rng_w[2 * k + 1];
         if (a.wz) {
@@ -1312,7 +1451,7 @@ __global__ __launch_bounds__(NT) void zpass_kernel(ZArgs<T> a) {
 // Bucket descriptors stay in global memory.  Pair tiles are not used here.
 // ---------------------------------------------------------------------------
 constexpr int RES_MAX_REG = 16;
-constexpr int FS_RES = FT_UHINGE | FT_GEN | FT_WIDE;
+constexpr int FS_RES = FT_UHINGE | FT_GEN | FT_WIDE | FT_XWIDE;
 
 struct ResRegion {
   const void* src;  // global source
@@ -1428,7 +1567,8 @@ __global__ void get_slots_kernel(int64_t ns, const int64_t* upos, const int32_t*
   out[i] = (double)u;
 }
 
-__global__ void fill_u16_kernel(int64_t n, uint16_t v, uint16_t* out) {
+template <typename W>
+__global__ void fill_kernel(int64_t n, W v, W* out) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) out[i] = v;
 }

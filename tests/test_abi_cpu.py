@@ -78,11 +78,22 @@ def test_driver_selection():
     inf = g.info()
     assert inf["driver"] == A.DRIVER_LAUNCHES and inf["n_pair_tiles"] == 1
     assert inf["resident_lds_bytes"] == 0
-    # large graphs: launches; the resident driver is refused
+    # large graphs: recorded iteration blocks (or launches when asked for);
+    # the resident driver is refused
     p = W.workload("packing_sq2000")
     g = A.Graph.from_problem(p, device=None)
     assert _finalize_cpu(g) in (A.OK, A.E_NO_DEVICE)
+    assert g.info()["driver"] == A.DRIVER_GRAPH
+    g = A.Graph.from_problem(p, device=None, driver=A.DRIVER_LAUNCHES)
+    assert _finalize_cpu(g) in (A.OK, A.E_NO_DEVICE)
     assert g.info()["driver"] == A.DRIVER_LAUNCHES
+    g = A.Graph.from_problem(p, device=None, driver=A.DRIVER_GRAPH, graph_block=8)
+    assert _finalize_cpu(g) in (A.OK, A.E_NO_DEVICE)
+    assert g.info()["driver"] == A.DRIVER_GRAPH
+    for bad in (1, 3, 5000, -2):
+        with pytest.raises(A.AdmmError) as e:
+            A.Graph.from_problem(p, device=None, graph_block=bad)
+        assert e.value.status == A.E_ARG
     g = A.Graph.from_problem(p, device=None, driver=A.DRIVER_RESIDENT)
     assert _finalize_cpu(g) == A.E_UNSUPPORTED
     # FP64 doubles the image: a graph that fits in FP32 may not in FP64
@@ -201,7 +212,8 @@ def test_validation_errors():
     _expect(A.E_ARG, g.set_rho, -1.0)
     _expect(A.E_ARG, g.set_alpha, 0.0)
     _expect(A.E_ARG, g.set_option, A.OPT_PAIR_ROWS, 48)
-    _expect(A.E_ARG, g.set_option, A.OPT_DRIVER, 3)
+    _expect(A.E_ARG, g.set_option, A.OPT_DRIVER, 4)
+    _expect(A.E_ARG, g.set_option, A.OPT_GRAPH_BLOCK, 7)
     _expect(A.E_ARG, g.set_option, A.OPT_PAIR_STATE, 2)
     _expect(A.E_ARG, g.set_option, 99, 1)
 
