@@ -30,6 +30,15 @@ def test_copies_parity(N, d, prec, iters, tol):
     _one_step(p, 40, prec, 1e-12 if prec == FP64 else 1e-5, driver=A.DRIVER_LAUNCHES)
 
 
+@pytest.mark.parametrize("N,d,seed,iters", [(60, 100, 613, 40), (40, 200, 614, 30)])
+@pytest.mark.parametrize("prec,tol", [(FP64, 1e-9), (FP32, 1e-4)])
+def test_copies_wide_parity(N, d, seed, iters, prec, tol):
+    """Margin factors with d > 64 (two-sweep path)."""
+    p = W.svm_copies(N, d, seed=seed)
+    _traj(p, iters, prec, tol, driver=A.DRIVER_LAUNCHES)
+    _one_step(p, 20, prec, 1e-12 if prec == FP64 else 1e-5, driver=A.DRIVER_LAUNCHES)
+
+
 @pytest.mark.parametrize("prec,iters,tol", [(FP64, 60, 1e-9), (FP32, 30, 1e-4)])
 def test_copies_resident_driver(prec, iters, tol):
     p = W.svm_copies(40, 3, seed=95)

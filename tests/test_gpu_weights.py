@@ -12,8 +12,9 @@ import pytest
 import oracle as O
 import workloads as W
 from paper_1603_02526_amd import admm as A
+from tests import parity as P
 from tests.helpers import rel, slot_z
-from tests.test_gpu_graph import _check, _conditioning
+from tests.test_gpu_graph import _check, _well_conditioned
 
 pytestmark = pytest.mark.gpu
 
@@ -60,22 +61,26 @@ def _slot_rho(p):
 def test_weighted_parity(name, prec, iters, tol, driver):
     p = _cases()[name]
     if name == "packing_200":
-        # random overlapping disks are chaotic: shorter horizons keep the
-        # oracle's own rounding sensitivity far below the tolerance
-        iters = 15 if prec == FP64 else 6
+        # 200 overlapping random disks are chaotic.  Under rounding-size
+        # noise on z and u every iteration the oracle's own u moves by
+        # 1.8e-6 (relative norm) after eight FP32 iterations and 8.4e-5
+        # after ten, where an earlier run of this test measured the GPU
+        # 1.03e-4 away: at ten iterations the oracle's own rounding
+        # sensitivity is the size of the tolerance.  Eight keeps it below
+        # tol/20 (the precondition below); FP64 takes fifteen (4e-13).
+        iters = 15 if prec == FP64 else 8
     try:
         g = A.Graph.from_problem(p, precision=prec, driver=driver)
     except A.AdmmError as e:
         assert driver == A.DRIVER_RESIDENT and e.status == A.E_UNSUPPORTED
         pytest.skip("graph too large for the resident driver")
-    sens = _conditioning(p, iters, prec)
-    assert sens < tol / 20, sens
+    sens = _well_conditioned(p, iters, prec, tol)
     o = O.OracleGraph(p)
     g.run(iters)
     o.run(iters)
-    _check(g, o, tol)
+    _check(g, o, tol, sens)
     # residuals are maxima of differences of z-sized quantities: their error
-    # scales with |z|
+    # is bounded by the element-wise error of x and z times their magnitude
     (r, s), (ro, so) = g.residuals(), o.residuals()
     zmax = np.max(np.abs(o.z)) + 1.0
     assert abs(r - ro) <= tol * zmax, (r, ro)
@@ -87,7 +92,8 @@ def test_weighted_parity(name, prec, iters, tol, driver):
     o.set_state(z, u)
     g.run(1)
     o.run(1)
-    _check(g, o, 1e-12 if prec == FP64 else 1e-5)
+    _check(g, o, 1e-12 if prec == FP64 else 1e-5,
+           P.sensitivity(p, 1, 1e-16 if prec == FP64 else 6e-8, z0=z, u0=u)[1])
     if any(q.alpha is not None for q in p.groups):
         assert g.info()["alpha_is_one"] == 0
         return          # the zero weighted dual sums need one alpha per variable
