@@ -394,6 +394,19 @@ admm_status admm_mlp_get_params(admm_mlp* n, float* host);
  * allocates a temporary workspace and synchronises the stream. */
 admm_status admm_mlp_fit_output_scaling(admm_mlp* n, const float* targets, int64_t rows,
                                         float sd_min, void* stream);
+/* admm_mlp_fit_output_scaling for callers that cannot allocate (code under
+ * hipGraph capture, serving loops, harnesses that forbid hipMalloc): the
+ * same statistics, computed in a fixed 8 MiB device workspace that the
+ * library holds on each device for the life of the process, with no
+ * allocation, free or synchronisation (asynchronous on `stream`).  The
+ * chunks are those of admm_mlp_fit_output_scaling (bit-identical results)
+ * as long as (chunks + 1) * n_out fit the workspace's 2^20 doubles, else
+ * fewer, longer chunks.  ADMM_E_UNSUPPORTED when n_out > 2^19.  Every call
+ * on one device shares the workspace: calls that overlap in time on one
+ * device (other streams, other threads) race and must be serialised by
+ * the caller. */
+admm_status admm_mlp_fit_output_scaling_noalloc(admm_mlp* n, const float* targets, int64_t rows,
+                                                float sd_min, void* stream);
 admm_status admm_mlp_set_output_scaling(admm_mlp* n, const float* mean, const float* sd);
 admm_status admm_mlp_get_output_scaling(admm_mlp* n, float* mean, float* sd);
 /* y [batch][n_out] = MLP(x [batch][n_in]) including the output affine;

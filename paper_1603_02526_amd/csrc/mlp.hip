@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <cmath>
 #include <memory>
+#include <mutex>
 #include <vector>
 
 #include "internal.h"
@@ -282,6 +283,35 @@ __global__ void adam_kernel(int64_t n, float* p, const float* g, float* m, float
 
 }  // namespace
 
+// Workspace of admm_mlp_fit_output_scaling_noalloc: a fixed array in device
+// memory, one copy per device for the life of the process, shared by every
+// call on that device.  Host code uses only its device address, looked up
+// once per device with that device current; the symbol itself is a host
+// stand-in and is never passed to a kernel or a copy.
+constexpr int64_t SCRATCH_DOUBLES = int64_t(1) << 20;   // 8 MiB
+static __device__ __align__(256) double scratch[SCRATCH_DOUBLES];
+
+namespace {
+constexpr int SCRATCH_MAX_DEVICES = 64;
+std::mutex scratch_mu;
+double* scratch_dev[SCRATCH_MAX_DEVICES] = {};
+
+// Device address of `scratch` on `device` (which must be current).
+admm_status scratch_address(int device, double** out) {
+  if (device < 0 || device >= SCRATCH_MAX_DEVICES)
+    return admmi::set_err(ADMM_E_ARG, "device %d out of range", device);
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  if (!scratch_dev[device]) {
+    void* p = nullptr;
+    ADMM_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return admmi::set_err(ADMM_E_HIP, "no device address for the workspace");
+    scratch_dev[device] = static_cast<double*>(p);
+  }
+  *out = scratch_dev[device];
+  return ADMM_OK;
+}
+}  // namespace
+
 struct admm_mlp {
   int device = 0;
   int n_in = 0, hid = 0, n_out = 0, max_batch = 0;
@@ -545,6 +575,36 @@ admm_status admm_mlp_fit_output_scaling(admm_mlp* n, const float* targets, int64
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   hipFree(tmp);
   if (e != hipSuccess) return admmi::set_err(ADMM_E_HIP, "output scaling: %s", hipGetErrorString(e));
+  ADMM_HIP(hipGetLastError());
+  return ADMM_OK;
+}
+
+admm_status admm_mlp_fit_output_scaling_noalloc(admm_mlp* n, const float* targets, int64_t rows,
+                                                float sd_min, void* stream) {
+  admmi::clear_err();
+  if (!n || !targets || rows < 1) return admmi::set_err(ADMM_E_ARG, "bad arguments");
+  if (!(sd_min > 0.f)) return admmi::set_err(ADMM_E_ARG, "sd_min must be > 0");
+  if (2 * (int64_t)n->n_out > SCRATCH_DOUBLES)
+    return admmi::set_err(ADMM_E_UNSUPPORTED,
+                          "n_out = %d: the fixed workspace holds at most %lld outputs", n->n_out,
+                          (long long)(SCRATCH_DOUBLES / 2));
+  ADMM_HIP(hipSetDevice(n->device));
+  double* ws = nullptr;
+  if (admm_status s = scratch_address(n->device, &ws)) return s;
+  // the chunking of admm_mlp_fit_output_scaling, with at most as many
+  // chunks as the workspace holds partial rows (one more row keeps the mean)
+  const int64_t nk = std::min<int64_t>(std::min<int64_t>(1024, (rows + 255) / 256),
+                                       SCRATCH_DOUBLES / n->n_out - 1);
+  const int64_t chunk = (rows + nk - 1) / nk;
+  const int nkk = (int)((rows + chunk - 1) / chunk);
+  double* mean_d = ws + (int64_t)nkk * n->n_out;
+  hipStream_t st = (hipStream_t)stream;
+  const dim3 gp((n->n_out + 255) / 256, nkk);
+  const unsigned gf = (n->n_out + 255) / 256;
+  colpart_kernel<<<gp, 256, 0, st>>>(rows, n->n_out, chunk, targets, nullptr, 1, ws);
+  colfinish_kernel<<<gf, 256, 0, st>>>(n->n_out, nkk, rows, ws, 0, mean_d, n->mu, n->sd, sd_min);
+  colpart_kernel<<<gp, 256, 0, st>>>(rows, n->n_out, chunk, targets, mean_d, 2, ws);
+  colfinish_kernel<<<gf, 256, 0, st>>>(n->n_out, nkk, rows, ws, 1, mean_d, n->mu, n->sd, sd_min);
   ADMM_HIP(hipGetLastError());
   return ADMM_OK;
 }

@@ -36,6 +36,8 @@ def _setup():
     L.admm_mlp_train_step.argtypes = [VP, VP, VP, ctypes.c_int32, ctypes.c_float, VP, VP]
     L.admm_mlp_fit_output_scaling.restype = st
     L.admm_mlp_fit_output_scaling.argtypes = [VP, VP, ctypes.c_int64, ctypes.c_float, VP]
+    L.admm_mlp_fit_output_scaling_noalloc.restype = st
+    L.admm_mlp_fit_output_scaling_noalloc.argtypes = [VP, VP, ctypes.c_int64, ctypes.c_float, VP]
     L.admm_mlp_set_output_scaling.restype = st
     L.admm_mlp_set_output_scaling.argtypes = [VP, FP, FP]
     L.admm_mlp_get_output_scaling.restype = st
@@ -86,6 +88,12 @@ class MLP:
     def fit_output_scaling(self, targets, sd_min: float = 1e-6, stream=None):
         check(_setup().admm_mlp_fit_output_scaling(self._h, _p(targets), int(targets.shape[0]),
                                                    float(sd_min), _stream(stream)))
+
+    def fit_output_scaling_noalloc(self, targets, sd_min: float = 1e-6, stream=None):
+        """As fit_output_scaling, in the library's fixed device workspace
+        (no allocation, asynchronous)."""
+        check(_setup().admm_mlp_fit_output_scaling_noalloc(
+            self._h, _p(targets), int(targets.shape[0]), float(sd_min), _stream(stream)))
 
     def set_output_scaling(self, mean, sd):
         m = np.ascontiguousarray(mean, dtype=np.float32)
