@@ -82,6 +82,10 @@ def lib(openmp: bool = False):
         L.orc_prox.argtypes = [ctypes.c_int, ctypes.c_int, ip, dp,
                                ctypes.c_int, ctypes.c_double, dp, dp]
         L.orc_threads.restype = ctypes.c_int
+        L.orc_set_twa.argtypes = [vp, ctypes.c_int]
+        L.orc_get_wr.argtypes = [vp, dp]
+        L.orc_prox_free.restype = ctypes.c_int
+        L.orc_prox_free.argtypes = [ctypes.c_int, dp, dp, dp, dp]
         L.orc_set_factor_weights.restype = ctypes.c_int
         L.orc_set_factor_weights.argtypes = [vp, ctypes.c_long, ctypes.c_long,
                                              ctypes.c_double, ctypes.c_double]
@@ -110,11 +114,23 @@ def prox(kind: str, dims, params, rho: float, nv) -> np.ndarray:
     return out
 
 
+def prox_free(kind: str, params, wl, nv) -> np.ndarray:
+    """Three-weight variant: the non-overlap or wall prox with received
+    weights ``wl`` per slot, at least one of them zero."""
+    params = np.ascontiguousarray(params if params is not None else [0.0], dtype=np.float64)
+    wl = np.ascontiguousarray(wl, dtype=np.float64).ravel()
+    nv = np.ascontiguousarray(nv, dtype=np.float64).ravel()
+    out = np.zeros_like(nv)
+    if lib().orc_prox_free(KIND[kind], _dp(params), _dp(wl), _dp(nv), _dp(out)) != 0:
+        raise ValueError(f"no three-weight prox for {kind}")
+    return out
+
+
 class OracleGraph:
     """Algorithm 2 in FP64 on a ``workloads.Problem``."""
 
     def __init__(self, problem, rho: Optional[float] = None,
-                 alpha: Optional[float] = None, openmp: bool = False):
+                 alpha: Optional[float] = None, openmp: bool = False, twa: bool = False):
         L = self._L = lib(openmp)
         dims = np.ascontiguousarray(problem.var_dims, dtype=np.int32)
         self._h = L.orc_graph_create(len(dims), _ip(dims))
@@ -138,6 +154,8 @@ class OracleGraph:
                          float(problem.alpha if alpha is None else alpha))
         self.n_slots = int(L.orc_num_slots(self._h))
         self.n_z = int(L.orc_num_z(self._h))
+        self.twa = bool(twa)
+        L.orc_set_twa(self._h, 1 if twa else 0)
         self.set_state(problem.z0)
 
     def __del__(self):
@@ -160,7 +178,16 @@ class OracleGraph:
         structure (the paper's second CPU scheme) instead of one parallel
         region per update.  Both give the same results bit for bit."""
         fn = self._L.orc_run_region if region else self._L.orc_run
-        return int(fn(self._h, int(iters), float(tol)))
+        done = int(fn(self._h, int(iters), float(tol)))
+        if done < 0:
+            raise ValueError("the one-region scheme runs plain Algorithm 2 only")
+        return done
+
+    @property
+    def wr(self) -> np.ndarray:
+        """Three-weight variant: the weight each factor sent on each edge slot
+        in the last x-update (0 or the edge's rho)."""
+        return self._get(self._L.orc_get_wr, self.n_slots)
 
     def _get(self, fn, n):
         out = np.zeros(n)

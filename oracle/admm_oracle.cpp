@@ -54,6 +54,26 @@
 //
 // Stopping measures (the paper leaves them open): after the u-update,
 //   r = max_e |x_e - z_b|        s = rho * max_b |z_b - z_b(previous)|.
+//
+// Three-weight variant (Sec. II names improved update schemes for the
+// per-edge weights, citing the three-weight message-passing algorithm of
+// Derbinsky et al.; the reading used here is listed in the design notes).
+// Every message carries a weight in {0, rho_(a,b), infinity}; no operator
+// here is ever certain of a value, so only 0 and rho occur:
+//   x-update: each factor's prox uses the weights of the messages it
+//     receives (left weights) and sets the weight of each message it
+//     sends (right weights): a non-overlap or wall factor whose constraint
+//     is inactive (the prox leaves n unchanged) sends weight 0 on all its
+//     edges, every other factor sends rho.  A zero left weight marks a
+//     variable no factor had an opinion on: among the factor's edges, the
+//     zero-weight ones then absorb the whole correction, in equal shares.
+//   z-update: z_b = sum w m / sum w over b's edges; when every weight is 0
+//     z_b keeps its value.  Every edge of b then receives left weight rho
+//     (its own) if some weight was positive, else 0.
+//   u-update: u_e += alpha (x_e - z_b) for edges sent with weight rho; u_e
+//     is reset to 0 for edges sent with weight 0 (an inactive constraint
+//     carries no multiplier).
+// With every weight equal to rho the iteration is Algorithm 2 exactly.
 
 #include <algorithm>
 #include <cmath>
@@ -104,6 +124,8 @@ struct Graph {
   long lists_for = -1;             // nslot the tables were built for
   double rho = 1.0, alpha = 1.0;
   double r_primal = 0.0, r_dual = 0.0;
+  bool twa = false;                 // three-weight variant
+  std::vector<double> wr, wl;       // per edge slot: sent and received weights
 };
 
 // ---------------------------------------------------------------------------
@@ -463,6 +485,100 @@ void iterate(Graph& g) {
   g.r_dual = s;
 }
 
+// Three-weight prox of the two constraint factors of circle packing with
+// received weights wl (per slot; the slots of one edge share their weight)
+// that include a zero.  The zero-weight edges take the correction in equal
+// shares (the limit of the weighted projection as their weights go to 0
+// together) and every other edge keeps its input.
+void prox_nonoverlap_free(const double* nv, const double* wl, double* out) {
+  const double c1x = nv[0], c1y = nv[1], r1 = nv[2];
+  const double c2x = nv[3], c2y = nv[4], r2 = nv[5];
+  const double dx = c2x - c1x, dy = c2y - c1y;
+  const double L = std::sqrt(dx * dx + dy * dy);
+  double hx = 1.0, hy = 0.0;
+  if (L > 0.0) { hx = dx / L; hy = dy / L; }
+  const double D = std::max(0.0, r1 + r2 - L);
+  // edges c1, r1, c2, r2 start at slots 0, 2, 3, 5
+  const bool z0 = wl[0] == 0.0, z1 = wl[2] == 0.0, z2 = wl[3] == 0.0, z3 = wl[5] == 0.0;
+  const double nzero = (z0 ? 1.0 : 0.0) + (z1 ? 1.0 : 0.0) + (z2 ? 1.0 : 0.0) + (z3 ? 1.0 : 0.0);
+  const double share = D / nzero;
+  out[0] = c1x - (z0 ? share : 0.0) * hx;
+  out[1] = c1y - (z0 ? share : 0.0) * hy;
+  out[2] = r1 - (z1 ? share : 0.0);
+  out[3] = c2x + (z2 ? share : 0.0) * hx;
+  out[4] = c2y + (z2 ? share : 0.0) * hy;
+  out[5] = r2 - (z3 ? share : 0.0);
+}
+
+void prox_wall_free(const double* nv, const double* p, const double* wl, double* out) {
+  const double Qx = p[0], Qy = p[1], Vx = p[2], Vy = p[3];
+  const double g = Qx * (nv[0] - Vx) + Qy * (nv[1] - Vy) - nv[2];
+  out[0] = nv[0]; out[1] = nv[1]; out[2] = nv[2];
+  if (g >= 0.0) return;
+  // edges c (slots 0, 1) and r (slot 2); equal weights on the free ones
+  const bool zc = wl[0] == 0.0, zr = wl[2] == 0.0;
+  const double den = (zc ? Qx * Qx + Qy * Qy : 0.0) + (zr ? 1.0 : 0.0);
+  const double lam = -g / den;
+  if (zc) { out[0] = nv[0] + lam * Qx; out[1] = nv[1] + lam * Qy; }
+  if (zr) out[2] = nv[2] - lam;
+}
+
+// One iteration of the three-weight variant, each update its own loop.
+void iterate_twa(Graph& g) {
+  const long S = g.nslot;
+  const long NF = static_cast<long>(g.F.size());
+  if (g.lists_for != S) build_lists(g);
+  if (static_cast<long>(g.wl.size()) != S) g.wl = g.erho;   // start: every weight rho
+  g.wr.resize(S);
+  for (long e = 0; e < S; ++e) g.n[e] = g.z[g.slot_z[e]] - g.u[e];
+  // x-update with received weights; sent weights
+  std::vector<int> dims;
+  for (long i = 0; i < NF; ++i) {
+    const Factor& f = g.F[i];
+    dims.resize(f.vars.size());
+    for (size_t k = 0; k < f.vars.size(); ++k) dims[k] = g.dim[f.vars[k]];
+    const long s0 = f.slot[0];
+    const double rho = f.rho > 0.0 ? f.rho : g.rho;
+    bool free_edge = false;
+    for (int q = 0; q < f.nslots; ++q) free_edge = free_edge || g.wl[s0 + q] == 0.0;
+    const bool constraint = f.kind == K_NONOVERLAP || f.kind == K_WALL;
+    if (constraint && free_edge) {
+      if (f.kind == K_NONOVERLAP) prox_nonoverlap_free(&g.n[s0], &g.wl[s0], &g.x[s0]);
+      else prox_wall_free(&g.n[s0], f.p.data(), &g.wl[s0], &g.x[s0]);
+    } else {
+      prox_apply(f.kind, static_cast<int>(f.vars.size()), dims.data(), f.p.data(),
+                 static_cast<int>(f.p.size()), rho, &g.n[s0], &g.x[s0]);
+    }
+    bool moved = !constraint;
+    for (int q = 0; q < f.nslots && !moved; ++q) moved = g.x[s0 + q] != g.n[s0 + q];
+    for (int q = 0; q < f.nslots; ++q) g.wr[s0 + q] = moved ? g.erho[s0 + q] : 0.0;
+  }
+  for (long e = 0; e < S; ++e) g.m[e] = g.x[e] + g.u[e];
+  // z-update with the sent weights; received weights for the next x-update
+  g.zprev = g.z;
+  for (long b = 0; b < g.nz; ++b) {
+    double num = 0.0, den = 0.0;
+    for (long q = g.zbeg[b]; q < g.zbeg[b + 1]; ++q) {
+      const long e = g.zedges[q];
+      num += g.wr[e] * g.m[e];
+      den += g.wr[e];
+    }
+    if (den > 0.0) g.z[b] = num / den;
+    for (long q = g.zbeg[b]; q < g.zbeg[b + 1]; ++q) {
+      const long e = g.zedges[q];
+      g.wl[e] = den > 0.0 ? g.erho[e] : 0.0;
+    }
+  }
+  // u-update: edges sent with weight 0 carry no multiplier
+  for (long e = 0; e < S; ++e)
+    g.u[e] = g.wr[e] > 0.0 ? g.u[e] + g.ealpha[e] * (g.x[e] - g.z[g.slot_z[e]]) : 0.0;
+  double r = 0.0, s = 0.0;
+  for (long e = 0; e < S; ++e) r = std::max(r, std::fabs(g.x[e] - g.z[g.slot_z[e]]));
+  for (long b = 0; b < g.nz; ++b) s = std::max(s, g.vrho[b] * std::fabs(g.z[b] - g.zprev[b]));
+  g.r_primal = r;
+  g.r_dual = s;
+}
+
 // The whole run as one parallel region (the paper's second CPU scheme,
 // Sec. III-A): the threads live for every iteration, each update type is a
 // work-shared loop over its own index, and the barrier at the end of each
@@ -621,6 +737,8 @@ void orc_set_state(void* h, const double* z, const double* u) {
   g->x.assign(g->nslot, 0.0);
   g->m.assign(g->nslot, 0.0);
   g->n.assign(g->nslot, 0.0);
+  g->wl.clear();
+  g->wr.clear();
 }
 
 // Run up to max_iter iterations; when tol > 0 stop at the first iteration
@@ -629,15 +747,32 @@ int orc_run(void* h, int max_iter, double tol) {
   Graph* g = static_cast<Graph*>(h);
   if (static_cast<long>(g->u.size()) != g->nslot) orc_set_state(h, g->z.data(), nullptr);
   for (int k = 1; k <= max_iter; ++k) {
-    iterate(*g);
+    if (g->twa) iterate_twa(*g);
+    else iterate(*g);
     if (tol > 0.0 && g->r_primal <= tol && g->r_dual <= tol) return k;
   }
   return max_iter;
 }
 
+// Three-weight variant on (1) or off (0).  Switching resets every received
+// weight to rho.
+void orc_set_twa(void* h, int on) {
+  Graph* g = static_cast<Graph*>(h);
+  g->twa = on != 0;
+  g->wl.clear();
+  g->wr.clear();
+}
+
+// Weights sent by the factors in the last three-weight x-update, per slot.
+void orc_get_wr(void* h, double* w) {
+  Graph* g = static_cast<Graph*>(h);
+  for (long e = 0; e < g->nslot; ++e) w[e] = e < static_cast<long>(g->wr.size()) ? g->wr[e] : 0.0;
+}
+
 // orc_run with the one-region scheme (run_region); the same results.
 int orc_run_region(void* h, int max_iter, double tol) {
   Graph* g = static_cast<Graph*>(h);
+  if (g->twa) return -1;   // the region scheme runs Algorithm 2 only
   if (static_cast<long>(g->u.size()) != g->nslot) orc_set_state(h, g->z.data(), nullptr);
   if (max_iter < 1) return 0;
   return run_region(*g, max_iter, tol);
@@ -667,6 +802,16 @@ void orc_residuals(void* h, double* r, double* s) {
   Graph* g = static_cast<Graph*>(h);
   *r = g->r_primal;
   *s = g->r_dual;
+}
+
+// The three-weight constraint prox with received weights wl (per slot; at
+// least one zero), for the tests that pin it.
+int orc_prox_free(int kind, const double* params, const double* wl, const double* nv,
+                  double* out) {
+  if (kind == K_NONOVERLAP) prox_nonoverlap_free(nv, wl, out);
+  else if (kind == K_WALL) prox_wall_free(nv, params, wl, out);
+  else return -1;
+  return 0;
 }
 
 // A single proximal operator, for the tests that pin each one.
