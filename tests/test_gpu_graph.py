@@ -40,10 +40,10 @@ def _check(g, o, tol, sens=None):
     element (tests/parity.py: z relative to |z|; u and x relative to the
     size of the operands they are formed from, since u = m - z cancels and
     its error scales with |z_b|, not |u|; per-entry allowance for the
-    oracle's own sensitivity when `sens` is given)."""
-    e = P.errors(g.z(), g.u(), g.x(), o.z, o.u, o.x, o.slot_z, sens)
-    bad = {k: v for k, v in e.items() if not v < tol}
-    assert not bad, (bad, e)
+    entries the oracle itself cannot resolve to tol/20 left to the norm when
+    `sens` is given)."""
+    e = P.errors(g.z(), g.u(), g.x(), o.z, o.u, o.x, o.slot_z, sens, tol)
+    P.check(e, tol)
     return e
 
 
@@ -112,11 +112,12 @@ def test_packing_tiles_ragged_fp32(N, shape, seed, rb):
                                             for j in range(i + 1, N)})
 
 
-@pytest.mark.parametrize("N,seed,iters", [(65, 12, 10), (200, 12, 8)])
+@pytest.mark.parametrize("N,seed,iters", [(65, 12, 8), (200, 12, 8)])
 def test_packing_tiles_fp32(N, seed, iters):
-    """200 overlapping disks: after ten iterations the oracle's own x moves
-    by 6e-6 (relative norm) under rounding-size noise, above the tol/20
-    precondition; eight keep it at 7e-7."""
+    """Overlapping random disks: after ten iterations the oracle's own u and
+    x move by 6e-6 to 9e-6 (relative norm, the largest of four noisy runs)
+    under rounding-size noise, above the tol/20 precondition; eight keep
+    it below."""
     p = W.packing(N, "square", 0.3 / np.sqrt(N), seed=seed)
     _traj(p, iters, FP32, 1e-4)
     _one_step(p, 40, FP32, 1e-5)
@@ -230,6 +231,32 @@ def test_degenerate_graphs():
     np.testing.assert_array_equal(g.z(), W.workload("packing_tri10").z0.astype(np.float32))
 
 
+@pytest.mark.parametrize("case", ["packing_tri10", "packing_200", "svm", "mpc"])
+@pytest.mark.parametrize("bad", [np.nan, np.inf])
+def test_nonfinite_state_reported(case, bad):
+    """A NaN or infinity set from the host reaches the residuals of the run,
+    which report ADMM_E_NUMERIC; the status stays until a new state is
+    imported (every layout: resident driver, sparse pair tiles, shared
+    hinge, linear dynamics)."""
+    p = {"packing_tri10": lambda: W.workload("packing_tri10"),
+         "packing_200": lambda: W.packing(200, "square", 0.02, seed=47),
+         "svm": lambda: W.svm(3000, 20, seed=13),
+         "mpc": lambda: W.mpc_graph(W.mpc_batch(1, seed=41)[0])}[case]()
+    g = A.Graph.from_problem(p)
+    z0 = np.array(p.z0, dtype=np.float64)
+    z0[len(z0) // 2] = bad
+    g.set_state(z0)
+    g.run(5)
+    for _ in range(2):
+        with pytest.raises(A.AdmmError) as e:
+            g.residuals()
+        assert e.value.status == A.E_NUMERIC
+    g.set_state(p.z0)
+    g.run(5)
+    r, s = g.residuals()
+    assert np.isfinite(r) and np.isfinite(s)
+
+
 def test_determinism_and_resume():
     p = W.packing(150, "square", 0.04, seed=12)
     a = A.Graph.from_problem(p)
@@ -302,10 +329,20 @@ def _one_step(problem, warm_iters, prec, tol, alpha=None, pair_rows=0, driver=A.
     o.run(steps)
     _, sens = P.sensitivity(problem, steps, _eps(prec), alpha, z0=z, u0=u)
     _check(g, o, tol, sens)
+    # r = max_e |x_e - z_b(e)|: the kernel's maximum equals the one of its
+    # own exported iterates, and against the oracle's r the bar is the
+    # iterates' own (tolerance at the scale of z plus, at the entries
+    # attaining either maximum, the allowance for what rounding alone moves
+    # them in the oracle)
     (r, s), (ro, so) = g.residuals(), o.residuals()
     zmax = np.max(np.abs(o.z)) + 1.0
-    assert abs(r - ro) <= tol * zmax and abs(s - so) <= tol * zmax, (r, ro, s, so)
     sz = slot_z(problem)
+    dg = np.abs(g.x() - g.z()[sz])
+    assert abs(r - dg.max()) <= 1e-6 * dg.max() + (1e-12 if prec == FP64 else 1e-7), (r, dg.max())
+    sx = sens["x"] + sens["z"][sz]
+    ar = P.K_SENS * (sx[np.argmax(dg)] + sx[np.argmax(np.abs(o.x - o.z[sz]))])
+    az = 2 * P.K_SENS * float(np.max(sens["z"], initial=0.0))
+    assert abs(r - ro) <= tol * zmax + ar and abs(s - so) <= tol * zmax + az, (r, ro, s, so, ar, az)
     us = np.bincount(sz, weights=g.u(), minlength=problem.n_scalars)
     zz = g.z()
     scale = np.bincount(sz, weights=np.abs(g.u()) + np.abs(zz[sz]),
