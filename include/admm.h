@@ -102,7 +102,7 @@ typedef struct {
   int32_t driver;              /* ADMM_DRIVER_LAUNCHES, _RESIDENT or _GRAPH */
   int32_t resident_lds_bytes;  /* LDS image of the resident driver (0 if unused) */
   int32_t sparse_pair_state;   /* 1: pair tiles keep unmoved pairs' m implicit */
-  int32_t reserved_;
+  int32_t three_weight;        /* 1: the three-weight variant (ADMM_OPT_THREE_WEIGHT) */
 } admm_graph_info;
 
 /* Message for the last failing call on this thread ("" if none). */
@@ -171,6 +171,29 @@ admm_status admm_graph_set_group_alpha(admm_graph* g, int32_t group, double alph
  *  is the same in every driver, and launches and graph give identical bits.
  *  ADMM_OPT_GRAPH_BLOCK: iterations per recorded block (even, 2..4096;
  *  0 = default 32).
+ *  ADMM_OPT_ZLIST: where the z-update finds the contributions of the disks
+ *  of 64-row pair tiles.  ADMM_ZLIST_AUTO (default) or 16, 32, 64: in
+ *  transposed lists, contribution j of scalar k at j * n + k with the
+ *  scalars in disk order, so that each tile's 192 row and 192 column
+ *  partial sums are contiguous; the z-pass sums 16, 32 or 64 lists per
+ *  block (auto: 32).  ADMM_ZLIST_ZMAJOR: each scalar's contributions
+ *  contiguous, as for every other variable (the tile partials are then
+ *  scattered stores).  Results differ only in the order of the z-sums.
+ *  ADMM_OPT_THREE_WEIGHT (0 or 1, default 0): Sec. II gives every edge its
+ *  own rho_(a,b) and names improved update schemes for them, citing the
+ *  three-weight message-passing algorithm.  With 1 every message carries a
+ *  weight 0 or rho: a non-overlap or wall factor whose constraint is
+ *  inactive (its prox leaves n unchanged) sends 0, every other factor rho;
+ *  z_b is the weighted mean of the incoming m and keeps its value when
+ *  every weight is 0; an edge sent with weight 0 has its u reset to 0; a
+ *  variable no factor weighted is received with weight 0, and a constraint
+ *  factor then moves only such edges, in equal shares.  Built for packing
+ *  graphs (non-overlap, wall and separable factors, one rho, alpha = 1;
+ *  dense pair tiles only with the sparse pair state, so FP64 or
+ *  ADMM_PAIR_STATE_DENSE graphs take the general layout), with the launch
+ *  and graph drivers: finalize returns ADMM_E_UNSUPPORTED otherwise.  After
+ *  a run every edge's state is explicit (an inactive edge's m is z, its u
+ *  0), so admm_get_u/x and split runs see the same arrays as one run.
  *  ADMM_OPT_PAIR_STATE: per-edge state of dense pair tiles.  With alpha = 1
  *  a pair whose prox leaves n unchanged (no overlap) ends the iteration with
  *  m = z, the consensus it started from (Alg. 2: m = x + u, u = m_old - z,
@@ -182,7 +205,8 @@ admm_status admm_graph_set_group_alpha(admm_graph* g, int32_t group, double alph
  *  ADMM_PAIR_STATE_DENSE reads and writes every pair's m every iteration
  *  (always the case in FP64 or with alpha != 1). */
 enum { ADMM_OPT_PAIR_ROWS = 1, ADMM_OPT_DRIVER = 2, ADMM_OPT_PAIR_STATE = 3,
-       ADMM_OPT_GRAPH_BLOCK = 4 };
+       ADMM_OPT_GRAPH_BLOCK = 4, ADMM_OPT_THREE_WEIGHT = 5, ADMM_OPT_ZLIST = 6 };
+enum { ADMM_ZLIST_AUTO = 0, ADMM_ZLIST_ZMAJOR = 1 };
 enum { ADMM_DRIVER_AUTO = 0, ADMM_DRIVER_LAUNCHES = 1, ADMM_DRIVER_RESIDENT = 2,
        ADMM_DRIVER_GRAPH = 3 };
 enum { ADMM_PAIR_STATE_AUTO = 0, ADMM_PAIR_STATE_DENSE = 1 };
@@ -243,7 +267,11 @@ admm_status admm_get_x(admm_graph* g, double* x, void* stream);
 /* Residuals of the last iteration run: r = max_e |x_e - z_b| and
  * s = rho max_b |z_b - z_b(previous iteration)| (the paper leaves the
  * stopping criterion open; these are the infinity-norm measures used
- * throughout this library). */
+ * throughout this library).  Synchronises the stream.  ADMM_E_STATE before
+ * any iteration since the last state import.  ADMM_E_NUMERIC when an x or
+ * z of the last iteration is NaN or infinite (a NaN anywhere propagates to
+ * both through the averages); the status is sticky: every later call
+ * returns it until admm_set_state imports a new state. */
 admm_status admm_get_residuals(admm_graph* g, double* r_primal,
                                double* r_dual, void* stream);
 

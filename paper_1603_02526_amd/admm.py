@@ -23,7 +23,8 @@ STATUS_NAMES = {0: "OK", 1: "E_ARG", 2: "E_STATE", 3: "E_NUMERIC", 4: "E_HIP",
 KIND = dict(nonoverlap=1, wall=2, radius=3, quad=4, box=5, hinge=6, l2=7,
             lindyn=8, lindyn0=9, minerr=10, equal=11, margin=12)
 FP32, FP64 = 0, 1
-OPT_PAIR_ROWS, OPT_DRIVER, OPT_PAIR_STATE, OPT_GRAPH_BLOCK = 1, 2, 3, 4
+OPT_PAIR_ROWS, OPT_DRIVER, OPT_PAIR_STATE, OPT_GRAPH_BLOCK, OPT_THREE_WEIGHT, OPT_ZLIST = 1, 2, 3, 4, 5, 6
+ZLIST_AUTO, ZLIST_ZMAJOR = 0, 1
 DRIVER_AUTO, DRIVER_LAUNCHES, DRIVER_RESIDENT, DRIVER_GRAPH = 0, 1, 2, 3
 PAIR_STATE_AUTO, PAIR_STATE_DENSE = 0, 1
 
@@ -41,7 +42,7 @@ class GraphInfo(ctypes.Structure):
         "algo_bytes_per_iter", "layout_bytes_per_iter")] + [
         ("precision", ctypes.c_int32), ("alpha_is_one", ctypes.c_int32),
         ("driver", ctypes.c_int32), ("resident_lds_bytes", ctypes.c_int32),
-        ("sparse_pair_state", ctypes.c_int32), ("reserved_", ctypes.c_int32)]
+        ("sparse_pair_state", ctypes.c_int32), ("three_weight", ctypes.c_int32)]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}
@@ -225,7 +226,8 @@ class Graph:
     def from_problem(cls, problem, precision: int = FP32, device: Optional[int] = 0,
                      rho: Optional[float] = None, alpha: Optional[float] = None,
                      pair_rows: int = 0, driver: int = DRIVER_AUTO,
-                     pair_state: int = PAIR_STATE_AUTO, graph_block: int = 0):
+                     pair_state: int = PAIR_STATE_AUTO, graph_block: int = 0,
+                     three_weight: bool = False, zlist: int = ZLIST_AUTO):
         """Build from an object with var_dims, groups (kind, var_ids, params,
         shared), rho, alpha and z0.  device=None skips finalize."""
         g = cls(problem.var_dims, precision)
@@ -245,6 +247,10 @@ class Graph:
             g.set_option(OPT_PAIR_STATE, pair_state)
         if graph_block:
             g.set_option(OPT_GRAPH_BLOCK, graph_block)
+        if three_weight:
+            g.set_option(OPT_THREE_WEIGHT, 1)
+        if zlist:
+            g.set_option(OPT_ZLIST, zlist)
         if device is not None:
             g.finalize(device)
             g.set_state(problem.z0)

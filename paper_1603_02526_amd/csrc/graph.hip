@@ -32,8 +32,8 @@ using namespace admmg;
 namespace admmg {
 
 int64_t zpass_blocks(const Plan& P) {
-  return (int64_t)P.var_b.size() + ((int64_t)P.var_w.size() + ZPB - 1) / ZPB +
-         ((int64_t)P.var_l.size() + NT - 1) / NT;
+  return ((int64_t)P.var_t.size() + P.t_lpb - 1) / P.t_lpb + (int64_t)P.var_b.size() +
+         ((int64_t)P.var_w.size() + ZPB - 1) / ZPB + ((int64_t)P.var_l.size() + NT - 1) / NT;
 }
 
 // Bytes of the resident driver's LDS image: every region rounded up to 16 B,
@@ -76,6 +76,8 @@ struct admm_graph {
   int32_t pair_rows = 0;  // rows per dense pair tile (0: chosen at finalize)
   int32_t driver = ADMM_DRIVER_AUTO;
   int32_t graph_block = 32;  // iterations per recorded block of the graph driver
+  int32_t twa = 0;           // three-weight variant
+  int32_t zlist = 0;         // contribution layout of pair-tile entities (ADMM_OPT_ZLIST)
   int32_t pair_state = ADMM_PAIR_STATE_AUTO;
   int64_t n_factors = 0, n_edges = 0, n_slots = 0;
   int state = 0;  // 0 building, 1 validated (no device), 2 ready
@@ -248,6 +250,8 @@ bool detect_complete_pairs(const admm_graph& g, const Group& gr, std::vector<int
 constexpr int HINGE_DMAX = NT - 1;
 int hinge_dmax(int d) { return d <= 32 ? 32 : d <= 64 ? 64 : 0; }
 
+constexpr int32_t DEFAULT_T_LPB = 32;   // transposed lists per z-pass block (measured best of 16, 32, 64)
+
 bool hinge_uniform(const Group& gr) {
   for (int64_t f = 1; f < gr.n; ++f)
     for (int e = 0; e < gr.arity; ++e)
@@ -275,6 +279,16 @@ admm_status build_plan(admm_graph& g, Plan& P, bool no_tiles) {
   // index-buffer slot that will receive its position in the z-major buffer.
   struct Emit { int64_t z; int64_t key; };
   std::vector<Emit> em;
+  // Pair-tile partials in the transposed layout (64-row tiles, one pair
+  // bucket): scalar z, slot j of its transposed list, index-buffer key,
+  // relative rho.  Entity e's slots: the column partial of tile (I', B) at
+  // j = I' (I' <= B), the row partial of tile (B, J) at j = J + 1 (J >= B),
+  // B = e / 64; its other contributions follow at j >= NBC + 1.
+  struct TEmit { int64_t z; int32_t j; int64_t key; double rw; };
+  std::vector<TEmit> tem;
+  std::vector<int64_t> tz;     // scalars of the transposed lists, list order
+  int32_t t_tiles = 0;         // tile slots per transposed list (NBC + 1)
+  int n_pair_buckets = 0;
   std::vector<double> deg(g.nz, 0.0);   // sum of relative rho over each scalar's edges
   std::vector<double> rmz(g.nz, 0.0);
   struct EmRange { size_t end; double rho; };
@@ -319,7 +333,11 @@ admm_status build_plan(admm_graph& g, Plan& P, bool no_tiles) {
     std::vector<int32_t> ezc, ezr, fe1, fe2;
     const bool separable = gr.kind == KD_RADIUS || gr.kind == KD_QUAD || gr.kind == KD_BOX ||
                            gr.kind == KD_L2 || gr.kind == KD_MINERR;
-    if (gr.kind == KD_NONOVERLAP && !P.no_tiles &&
+    // the three-weight variant runs on pair tiles only with their sparse state
+    const bool tiles_ok = !P.no_tiles &&
+                          (!g.twa || (g.precision == ADMM_FP32 && P.alpha_one &&
+                                      g.pair_state != ADMM_PAIR_STATE_DENSE));
+    if (gr.kind == KD_NONOVERLAP && tiles_ok &&
         detect_complete_pairs(g, gr, ezc, ezr, fe1, fe2)) {
       // ---------------- dense pair tiles ----------------
       b.mode = BM_PAIR;
@@ -365,6 +383,18 @@ admm_status build_plan(admm_graph& g, Plan& P, bool no_tiles) {
       b.blk0 = (int32_t)blocks;
       blocks += b.n;
       b.blk1 = (int32_t)blocks;
+      // 64-row tiles of the only pair bucket write their partials into
+      // transposed lists: each tile's 192 row and 192 column partials land
+      // at consecutive positions
+      const bool tlay = RB == CB && ++n_pair_buckets == 1 && g.zlist != ADMM_ZLIST_ZMAJOR;
+      if (tlay) {
+        t_tiles = NBC + 1;
+        for (int e = 0; e < b.E; ++e) {
+          tz.push_back(ezc[e]);
+          tz.push_back(ezc[e] + 1);
+          tz.push_back(ezr[e]);
+        }
+      }
       // contributions: per tile, rows then columns with at least one pair
       for (int64_t t = 0; t < b.n; ++t) {
         const int I = tI[t], J = tJ[t];
@@ -373,17 +403,27 @@ admm_status build_plan(admm_graph& g, Plan& P, bool no_tiles) {
         for (int li = 0; li < RB; ++li) {
           const int ei = I * RB + li;
           if (ei >= b.E || ei >= maxej) break;
-          em.push_back({ezc[ei], pb + li * 3});
-          em.push_back({ezc[ei] + 1, pb + li * 3 + 1});
-          em.push_back({ezr[ei], pb + li * 3 + 2});
+          if (tlay) {
+            for (int c = 0; c < 3; ++c)
+              tem.push_back({c < 2 ? ezc[ei] + c : ezr[ei], J + 1, pb + li * 3 + c, rw});
+          } else {
+            em.push_back({ezc[ei], pb + li * 3});
+            em.push_back({ezc[ei] + 1, pb + li * 3 + 1});
+            em.push_back({ezr[ei], pb + li * 3 + 2});
+          }
         }
         for (int lj = 0; lj < CB; ++lj) {
           const int ej = J * CB + lj;
           if (ej >= b.E) break;
           if (ej <= I * RB) continue;
-          em.push_back({ezc[ej], pb + 3 * RB + lj * 3});
-          em.push_back({ezc[ej] + 1, pb + 3 * RB + lj * 3 + 1});
-          em.push_back({ezr[ej], pb + 3 * RB + lj * 3 + 2});
+          if (tlay) {
+            for (int c = 0; c < 3; ++c)
+              tem.push_back({c < 2 ? ezc[ej] + c : ezr[ej], I, pb + 3 * RB + lj * 3 + c, rw});
+          } else {
+            em.push_back({ezc[ej], pb + 3 * RB + lj * 3});
+            em.push_back({ezc[ej] + 1, pb + 3 * RB + lj * 3 + 1});
+            em.push_back({ezr[ej], pb + 3 * RB + lj * 3 + 2});
+          }
         }
       }
       for (int64_t f = 0; f < gr.n; ++f) {
@@ -705,11 +745,27 @@ admm_status build_plan(admm_graph& g, Plan& P, bool no_tiles) {
   // when that at most doubles their space (else explicit ranges), and short
   // lists a stride of LANE_MAX: the z-pass then reads them without first
   // reading a range.  Padding is never written and stays zero.
-  P.n_zc = (int64_t)em.size();
+  // Transposed lists first: tile slots, then the scalar's other
+  // contributions in emission order; every list padded to the longest.
+  P.n_zc = (int64_t)em.size() + (int64_t)tem.size();
+  std::vector<int64_t> tk(g.nz, -1);   // scalar -> transposed list
+  for (size_t k = 0; k < tz.size(); ++k) tk[tz[k]] = (int64_t)k;
   std::vector<int64_t> len(g.nz, 0);
   for (auto& e : em) len[e.z]++;
+  const int64_t n_t = (int64_t)tz.size();
+  int64_t t_rest = 0;
+  for (int64_t k = 0; k < n_t; ++k) t_rest = std::max(t_rest, len[tz[k]]);
+  P.t_len = n_t ? (int32_t)(t_tiles + t_rest) : 0;
+  P.t_lpb = g.zlist >= 16 ? g.zlist : DEFAULT_T_LPB;
+  P.t_base = 0;
+  const int64_t t_span = round_up(n_t * P.t_len, 16);
+  for (int64_t k = 0; k < n_t; ++k) {
+    P.var_t.push_back((int32_t)tz[k]);
+    P.deg_t.push_back(deg[tz[k]]);
+  }
   int64_t sum_w = 0, max_w = 0, n_wl = 0, n_ll = 0, sum_b = 0;
   for (int64_t zi = 0; zi < g.nz; ++zi) {
+    if (tk[zi] >= 0) continue;
     if (len[zi] > ZB_MIN) sum_b += len[zi];
     else if (len[zi] > LANE_MAX) { sum_w += len[zi]; max_w = std::max(max_w, len[zi]); ++n_wl; }
     else ++n_ll;
@@ -717,15 +773,17 @@ admm_status build_plan(admm_graph& g, Plan& P, bool no_tiles) {
   const int64_t S_w = round_up(std::max<int64_t>(max_w, 1), ZSEG);
   const bool pad_w = n_wl > 0 && S_w * n_wl <= 2 * sum_w + 4096;
   P.w_stride = pad_w ? S_w : 0;
-  P.w_base = round_up(sum_b, 16);
+  P.w_base = round_up(t_span + sum_b, 16);
   P.l_base = round_up(P.w_base + (pad_w ? S_w * n_wl : sum_w), 16);
   const int64_t zc_total = P.l_base + LANE_MAX * n_ll;
   std::vector<int64_t> base(g.nz, 0);
   {
-    int64_t pb = 0, pw = P.w_base, kw = 0, kl = 0;
+    int64_t pb = t_span, pw = P.w_base, kw = 0, kl = 0;
     for (int64_t zi = 0; zi < g.nz; ++zi) {
       const int64_t L = len[zi];
-      if (L > ZB_MIN) {
+      if (tk[zi] >= 0) {
+        base[zi] = t_tiles;   // next free slot of the transposed list
+      } else if (L > ZB_MIN) {
         base[zi] = pb;
         P.var_b.push_back((int32_t)zi);
         P.rng_b.push_back(pb);
@@ -756,12 +814,17 @@ admm_status build_plan(admm_graph& g, Plan& P, bool no_tiles) {
     size_t gi = 0;
     for (size_t q = 0; q < em.size(); ++q) {
       const Emit& e = em[q];
-      const int64_t pos = base[e.z]++;
+      const int64_t pos = tk[e.z] >= 0 ? P.t_base + (base[e.z]++) * n_t + tk[e.z] : base[e.z]++;
       P.idx[e.key] = (int32_t)pos;
       if (P.weighted) {
         while (q >= em_rho[gi].end) ++gi;
         P.wz[pos] = em_rho[gi].rho;
       }
+    }
+    for (const TEmit& e : tem) {
+      const int64_t pos = P.t_base + (int64_t)e.j * n_t + tk[e.z];
+      P.idx[e.key] = (int32_t)pos;
+      if (P.weighted) P.wz[pos] = e.rw;
     }
   }
   // pool = [contributions | m regions | x regions], each region aligned
@@ -929,6 +992,15 @@ admm_status admm_graph_set_option(admm_graph* g, int32_t option, int64_t value) 
                               "driver must be 0 (auto), 1 (launches), 2 (resident) or 3 (graph)");
       g->driver = (int32_t)value;
       return ADMM_OK;
+    case ADMM_OPT_ZLIST:
+      if (value != 0 && value != ADMM_ZLIST_ZMAJOR && value != 16 && value != 32 && value != 64)
+        return admmi::set_err(ADMM_E_ARG, "z-list layout must be 0, 1, 16, 32 or 64");
+      g->zlist = (int32_t)value;
+      return ADMM_OK;
+    case ADMM_OPT_THREE_WEIGHT:
+      if (value != 0 && value != 1) return admmi::set_err(ADMM_E_ARG, "three-weight must be 0 or 1");
+      g->twa = (int32_t)value;
+      return ADMM_OK;
     case ADMM_OPT_GRAPH_BLOCK:
       if (value != 0 && (value < 2 || value > 4096 || (value & 1)))
         return admmi::set_err(ADMM_E_ARG, "graph block must be 0 (default) or even in [2, 4096]");
@@ -945,8 +1017,10 @@ admm_status admm_graph_finalize(admm_graph* g, int32_t device) {
   if (g->state == 2) return admmi::set_err(ADMM_E_STATE, "graph already finalized");
   const int64_t es_ = g->precision == ADMM_FP64 ? 8 : 4;
   // Resident candidates: the m and x regions alone must fit the LDS image.
+  if (g->twa && g->driver == ADMM_DRIVER_RESIDENT)
+    return admmi::set_err(ADMM_E_UNSUPPORTED, "the three-weight variant runs with launches or graph blocks");
   bool want_res = (g->driver == ADMM_DRIVER_AUTO || g->driver == ADMM_DRIVER_RESIDENT) &&
-                  g->n_slots * 2 * es_ <= RES_LDS_BYTES;
+                  !g->twa && g->n_slots * 2 * es_ <= RES_LDS_BYTES;
   if (g->driver == ADMM_DRIVER_RESIDENT && !want_res)
     return admmi::set_err(ADMM_E_UNSUPPORTED, "resident driver: %lld slots do not fit in LDS",
                           (long long)g->n_slots);
@@ -966,6 +1040,21 @@ admm_status admm_graph_finalize(admm_graph* g, int32_t device) {
   }
   const Plan& P = g->plan;
   const int64_t es = g->precision == ADMM_FP64 ? 8 : 4;
+  if (g->twa) {
+    // the three-weight variant is built for packing graphs: non-overlap
+    // (pair tiles with their sparse state, or general), wall and separable
+    // factors, one rho and alpha = 1
+    if (!P.alpha_one || P.weighted)
+      return admmi::set_err(ADMM_E_UNSUPPORTED, "the three-weight variant needs alpha = 1 and one rho");
+    for (const BucketDesc& b : P.bt) {
+      const bool ok = (b.mode == BM_PAIR && b.sparse) || b.mode == BM_GEN_SLOT ||
+                      (b.mode == BM_GEN_FACTOR && (b.kind == KD_NONOVERLAP || b.kind == KD_WALL));
+      if (!ok)
+        return admmi::set_err(ADMM_E_UNSUPPORTED,
+                              "the three-weight variant supports non-overlap, wall and separable "
+                              "factors (kind %d is not one)", (int)b.kind);
+    }
+  }
   admm_graph_info& I = g->info;
   I.n_vars = (int64_t)g->dim.size();
   I.n_scalars = g->nz;
@@ -987,6 +1076,7 @@ admm_status admm_graph_finalize(admm_graph* g, int32_t device) {
   const int32_t eager = g->driver == ADMM_DRIVER_LAUNCHES ? ADMM_DRIVER_LAUNCHES : ADMM_DRIVER_GRAPH;
   I.driver = P.resident ? ADMM_DRIVER_RESIDENT : eager;
   I.sparse_pair_state = P.n_flags > 0 ? 1 : 0;
+  I.three_weight = g->twa;
   I.resident_lds_bytes = P.resident ? (int32_t)resident_image_bytes(P, g->nz, es) : 0;
   if (admm_status s = admmi::probe_device(device)) {
     g->state = 1;
@@ -1005,6 +1095,7 @@ admm_status admm_graph_finalize(admm_graph* g, int32_t device) {
     }
   }
   eng->graph_block = I.driver == ADMM_DRIVER_GRAPH ? g->graph_block : 0;
+  eng->twa = g->twa != 0;
   std::vector<double> z0(g->nz, 0.0);
   if (admm_status s = eng->upload(P, z0, g->rho, g->alpha)) return s;
   g->eng = std::move(eng);

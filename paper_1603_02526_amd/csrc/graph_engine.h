@@ -6,6 +6,7 @@
 #pragma once
 
 #include <algorithm>
+#include <cmath>
 #include <vector>
 
 #include <hip/hip_ext.h>
@@ -53,6 +54,15 @@ struct Engine : EngineBase {
   double* io = nullptr;
   int64_t io_n = 0;
   bool have_resid = false;
+  int32_t* var_t = nullptr;     // transposed z lists (pair-tile entities)
+  T* deg_t = nullptr;
+  int64_t n_t = 0, t_base = 0;
+  int32_t t_len = 0, t_lpb = 64;
+  T* wc = nullptr;              // three-weight variant: weight per contribution position
+  uint8_t* zfree = nullptr;     // three-weight variant: per z scalar, no edge weighted
+  uint8_t* twb = nullptr;       // three-weight variant: per constraint factor, sent rho
+  int64_t n_twb = 0;
+  bool numeric_fail = false;  // sticky until the next state import
   std::vector<void*> allocs;
 
   ~Engine() override {
@@ -168,7 +178,9 @@ struct Engine : EngineBase {
           need |= FT_GEN;
         else need |= FT_WIDE;
       }
-      fs = ((need & ~FS_PAIR) == 0)     ? FS_PAIR
+      if (twa) need |= FT_TWA;
+      fs = (need & FT_TWA) ? ((need & FT_PAIRSP) ? FS_PAIRSP_TW : FS_GEN_TW)
+           : ((need & ~FS_PAIR) == 0)   ? FS_PAIR
            : ((need & ~FS_PAIRSP) == 0) ? FS_PAIRSP
            : ((need & ~FS_HINGE) == 0)  ? FS_HINGE
            : ((need & ~FS_XW) == 0)     ? FS_XW
@@ -195,9 +207,26 @@ struct Engine : EngineBase {
     ADMM_HIP(hipMemset(pool, 0, (size_t)std::max<int64_t>(pool_n, 1) * sizeof(T)));
     if ((s = put_conv(&par, P.par))) return s;
     if ((s = put(&idx, P.idx))) return s;
-    if ((s = put(&bt, P.bt))) return s;
+    {
+      // three-weight variant: each constraint factor of the general layout
+      // keeps one byte (whether it sent weight rho in the last iteration)
+      std::vector<BucketDesc> btc = P.bt;
+      n_twb = 0;
+      for (BucketDesc& b : btc) {
+        b.twb_off = n_twb;
+        if (twa && b.mode == BM_GEN_FACTOR && (b.kind == KD_NONOVERLAP || b.kind == KD_WALL))
+          n_twb += b.n;
+      }
+      if ((s = put(&bt, btc))) return s;
+    }
     if ((s = alloc(&z[0], nz))) return s;
     if ((s = alloc(&z[1], nz))) return s;
+    n_t = (int64_t)P.var_t.size();
+    t_base = P.t_base;
+    t_len = P.t_len;
+    t_lpb = P.t_lpb;
+    if ((s = put(&var_t, P.var_t))) return s;
+    if ((s = put_conv(&deg_t, P.deg_t))) return s;
     if ((s = put(&var_b, P.var_b))) return s;
     if ((s = put(&rng_b, P.rng_b))) return s;
     if ((s = put_conv(&deg_b, P.deg_b))) return s;
@@ -221,6 +250,17 @@ struct Engine : EngineBase {
     if ((s = alloc(&io, io_n))) return s;
     n_flags = P.n_flags;
     if ((s = alloc(&flags, n_flags))) return s;
+    if (twa) {
+      // weights written with the contributions; those of separable factors
+      // (always weight rho) once here, the others by every x-pass
+      std::vector<T> w0((size_t)std::max<int64_t>(P.zc_span, 1), T(0));
+      for (const BucketDesc& b : P.bt)
+        if (b.mode == BM_GEN_SLOT)
+          for (int64_t q = 0; q < b.n; ++q) w0[(size_t)P.idx[b.dst_off + q]] = T(1);
+      if ((s = put(&wc, w0))) return s;
+      if ((s = alloc(&zfree, nz))) return s;
+      if ((s = alloc(&twb, n_twb))) return s;
+    }
     if (resident) resident_layout();
     return set_state(z0.data(), nullptr, nullptr);
   }
@@ -238,12 +278,18 @@ struct Engine : EngineBase {
     if (gs)
       set_state_kernel<T><<<gs, 256, 0, st>>>(n_slots, upos, uz, uh ? io : nullptr, z[zc], pool,
                                               xdelta, 1);
+    // three-weight variant: a state import starts from weight rho everywhere
+    if (zfree && nz)
+      fill_kernel<uint8_t><<<(unsigned)((nz + 255) / 256), 256, 0, st>>>(nz, (uint8_t)0, zfree);
+    if (twb && n_twb)
+      fill_kernel<uint8_t><<<(unsigned)((n_twb + 255) / 256), 256, 0, st>>>(n_twb, (uint8_t)1, twb);
     // every pair's m is explicit in the dense arrays after a state import
     if (n_flags)
       fill_kernel<uint16_t><<<(unsigned)((n_flags + 255) / 256), 256, 0, st>>>(n_flags, (uint16_t)0xFFFF, flags);
     ADMM_HIP(hipGetLastError());
     ADMM_HIP(hipStreamSynchronize(st));
     have_resid = false;
+    numeric_fail = false;
     return ADMM_OK;
   }
 
@@ -256,6 +302,9 @@ struct Engine : EngineBase {
     a.zprev = z[zc ^ 1];
     a.flags = flags;
     a.blockmax = bmx;
+    a.wc = wc;
+    a.zfree = zfree;
+    a.twb = twb;
     a.bt = bt;
     a.nb = nb;
     a.alpha = alpha;
@@ -294,12 +343,24 @@ struct Engine : EngineBase {
     else if (fs == FS_HINGE) launch_x_fs<A1, FS_HINGE>(mode, st, e0, e1);
     else if (fs == FS_XW) launch_x_fs<A1, FS_XW>(mode, st, e0, e1);
     else if (fs == FS_ALL) launch_x_fs<A1, FS_ALL>(mode, st, e0, e1);
-    else launch_x_fs<A1, FS_ALLX>(mode, st, e0, e1);
+    else if (fs == FS_ALLX) launch_x_fs<A1, FS_ALLX>(mode, st, e0, e1);
+    else if constexpr (A1) {
+      // the three-weight variant runs with alpha = 1 only
+      if (fs == FS_PAIRSP_TW) launch_x_fs<A1, FS_PAIRSP_TW>(mode, st, e0, e1);
+      else launch_x_fs<A1, FS_GEN_TW>(mode, st, e0, e1);
+    }
   }
 
   ZArgs<T> zargs(int check) const {
     ZArgs<T> a;
     a.pool = pool;
+    a.var_t = var_t;
+    a.deg_t = deg_t;
+    a.n_t = n_t;
+    a.t_base = t_base;
+    a.nb_t = (int32_t)((n_t + t_lpb - 1) / t_lpb);
+    a.t_len = t_len;
+    a.t_lpb = t_lpb;
     a.var_b = var_b;
     a.rng_b = rng_b;
     a.deg_b = deg_b;
@@ -321,6 +382,8 @@ struct Engine : EngineBase {
     a.zout = z[zc ^ 1];
     a.blockmax = bmz;
     a.check = check;
+    a.wc = wc;
+    a.zfree = zfree;
     return a;
   }
 
@@ -514,6 +577,8 @@ struct Engine : EngineBase {
 
   admm_status residuals(double* r, double* s, hipStream_t st) override {
     if (!have_resid) return admmi::set_err(ADMM_E_STATE, "no iteration has been run since the last state change");
+    if (numeric_fail)
+      return admmi::set_err(ADMM_E_NUMERIC, "an iterate became NaN or infinite (set a new state)");
     ADMM_HIP(hipSetDevice(device));
     std::vector<T> hx(std::max<int64_t>(xblocks, 1), T(0)), hz(std::max<int64_t>(zblocks, 1), T(0));
     if (xblocks) ADMM_HIP(hipMemcpyAsync(hx.data(), bmx, xblocks * sizeof(T), hipMemcpyDeviceToHost, st));
@@ -525,6 +590,13 @@ struct Engine : EngineBase {
     *r = (double)a;
     // weighted graphs scale each variable's change by its largest rho in the kernel
     *s = weighted ? (double)b : (double)b / (double)inv_rho;
+    // every block maximum turns a NaN into +infinity: a non-finite residual
+    // means some x or z of the last iteration is not finite
+    if (!std::isfinite(*r) || !std::isfinite(*s)) {
+      numeric_fail = true;
+      return admmi::set_err(ADMM_E_NUMERIC, "an iterate became NaN or infinite (r = %g, s = %g)",
+                            *r, *s);
+    }
     return ADMM_OK;
   }
 

@@ -62,6 +62,7 @@ struct BucketDesc {
                         // of the bucket, which takes one partial sum per workgroup
   int32_t ub_pad;
   int64_t m_off, x_off;  // element offsets of the state regions in the pool
+  int64_t twb_off;      // three-weight variant: first byte of this bucket's active flags
   int64_t dst_off;      // index-buffer offset of the contribution destinations
   int64_t idx_off;      // offset in the int32 index buffer
   int64_t par_off;      // element offset in the parameter buffer
@@ -81,11 +82,21 @@ struct XArgs {
   const BucketDesc* bt;
   int32_t nb;
   T alpha, inv_rho;
+  // three-weight variant (null otherwise): per contribution position the
+  // weight written with it, per z scalar "no edge weighted" from the last
+  // z-update, per constraint factor "sent weight rho" in the last x-update
+  T* wc;
+  const uint8_t* zfree;
+  uint8_t* twb;
 };
 
 template <typename T>
 struct ZArgs {
   const T* pool;
+  const int32_t* var_t;   // transposed lists (pair-tile entities): 64 per block
+  const T* deg_t;
+  int64_t n_t, t_base;
+  int32_t nb_t, t_len, t_lpb;  // blocks, padded length, lists per block (16, 32 or 64)
   const int32_t* var_b;   // lists of more than ZB_MIN contributions: one block each
   const int64_t* rng_b;
   const T* deg_b;
@@ -105,6 +116,10 @@ struct ZArgs {
   const T* wz;            // per contribution position: its edge's rho (null: all equal)
   const T* rmz;           // per z scalar: the largest rho of its edges (with wz)
   int32_t check;
+  // three-weight variant (null otherwise): z = sum(contributions) /
+  // sum(weights written with them), z kept and zfree set when every weight is 0
+  const T* wc;
+  uint8_t* zfree;
 };
 
 template <typename T>
@@ -115,10 +130,13 @@ template <typename T>
 __device__ __forceinline__ T tmin(T a, T b) { return a < b ? a : b; }
 
 // Block-wide max of non-negative values, stored by thread 0 at *out (the
-// caller points out at its block's slot).
+// caller points out at its block's slot).  A NaN enters as +infinity, so a
+// non-finite iterate anywhere in the block always reaches the result (a
+// plain max can drop a NaN operand).
 template <typename T>
 __device__ __forceinline__ void block_max_store(T v, T* out) {
   __shared__ T red[NT / 64];
+  if (!(v == v)) v = T(INFINITY);
   v = admmi::wave_max(v);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
   __syncthreads();
@@ -179,9 +197,10 @@ __device__ __forceinline__ bool prox_nonoverlap(T* v) {
   return moved;
 }
 
-// Wall Q^T(c - V) >= r; p = (Qx, Qy, Q.V, 1/(|Q|^2+1)).
+// Wall Q^T(c - V) >= r; p = (Qx, Qy, Q.V, 1/(|Q|^2+1)).  Returns whether
+// the constraint was active (the prox moved its input).
 template <typename T>
-__device__ __forceinline__ void prox_wall(T* v, T qx, T qy, T qv, T ik) {
+__device__ __forceinline__ bool prox_wall(T* v, T qx, T qy, T qv, T ik) {
   const T g = qx * v[0] + qy * v[1] - qv - v[2];
   if (g < T(0)) {
     const T st = -g * ik;
@@ -189,6 +208,47 @@ __device__ __forceinline__ void prox_wall(T* v, T qx, T qy, T qv, T ik) {
     v[1] += st * qy;
     v[2] -= st;
   }
+  return g < T(0);
+}
+
+// Three-weight variant (Sec. II's per-edge weights; every message weight is
+// 0 or rho).  An edge received with weight 0 belongs to a variable no
+// factor weighted in the last z-update; the zero-weight edges of a
+// constraint factor absorb its whole correction in equal shares and the
+// other edges keep their input.  Non-overlap: bits of fr = c1, r1, c2, r2
+// received with weight 0 (at least one set).
+template <typename T>
+__device__ __forceinline__ bool prox_nonoverlap_free(T* v, unsigned fr) {
+  const T dx = v[3] - v[0], dy = v[4] - v[1];
+  const T L = tsqrt(dx * dx + dy * dy);
+  const T D = v[2] + v[5] - L;
+  const bool moved = D > T(0);
+  if (moved) {
+    T hx = T(1), hy = T(0);
+    if (L > T(0)) {
+      const T il = trcp(L);
+      hx = dx * il;
+      hy = dy * il;
+    }
+    const T st = D / T(__popc(fr));
+    if (fr & 1u) { v[0] -= st * hx; v[1] -= st * hy; }
+    if (fr & 2u) v[2] -= st;
+    if (fr & 4u) { v[3] += st * hx; v[4] += st * hy; }
+    if (fr & 8u) v[5] -= st;
+  }
+  return moved;
+}
+
+// Wall with bits of fr = c, r received with weight 0 (at least one set).
+template <typename T>
+__device__ __forceinline__ bool prox_wall_free(T* v, T qx, T qy, T qv, unsigned fr) {
+  const T g = qx * v[0] + qy * v[1] - qv - v[2];
+  if (!(g < T(0))) return false;
+  const T den = ((fr & 1u) ? qx * qx + qy * qy : T(0)) + ((fr & 2u) ? T(1) : T(0));
+  const T lam = -g / den;
+  if (fr & 1u) { v[0] += lam * qx; v[1] += lam * qy; }
+  if (fr & 2u) v[2] -= lam;
+  return true;
 }
 
 // ---------------------------------------------------------------------------
@@ -375,7 +435,7 @@ __device__ __forceinline__ float pair_colsum(float (&cs)[4][3], float (*cacc)[PB
   return sum;
 }
 
-template <int MODE, int RB>
+template <int MODE, int RB, bool TW = false>
 __device__ __forceinline__ void xpass_pair_v4(const XArgs<float>& a, const BucketDesc& b,
                                               int tile) {
   using PM = PairMap<RB>;
@@ -442,6 +502,31 @@ __device__ __forceinline__ void xpass_pair_v4(const XArgs<float>& a, const Bucke
       }
     }
     block_max_store(rmax, a.blockmax);
+    if constexpr (TW) {
+      // three-weight variant: pairs the last iteration did not move sent
+      // weight 0, so their dual is 0 and their m is the final z; then every
+      // pair's m is explicit again
+      uint16_t* flagp = a.flags + b.flag0 + (int64_t)tile * NT + t;
+      const uint32_t fl = *flagp;
+      float* mt = a.pool + b.m_off + (int64_t)tile * TS;
+#pragma unroll
+      for (int k = 0; k < PRT; ++k) {
+        const int li = PM::row(w, k, rg);
+        if (((fl >> (4 * k)) & 0xFu) == 0xFu) continue;
+        f4v m4[6];
+#pragma unroll
+        for (int s = 0; s < 6; ++s) m4[s] = *(const f4v*)(mt + s * TSZ + li * CB + 4 * cq);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          if ((fl >> (4 * k + c)) & 1u) continue;
+#pragma unroll
+          for (int s = 0; s < 6; ++s) m4[s][c] = s < 3 ? zrow4[li * 3 + s] : zcl[c][s - 3];
+        }
+#pragma unroll
+        for (int s = 0; s < 6; ++s) *(f4v*)(mt + s * TSZ + li * CB + 4 * cq) = m4[s];
+      }
+      *flagp = 0xFFFFu;
+    }
   } else {
     float* mt = a.pool + b.m_off + (int64_t)tile * TS;
     float* xt = a.pool + b.x_off + (int64_t)tile * TS;
@@ -523,7 +608,14 @@ __device__ __forceinline__ void xpass_pair_v4(const XArgs<float>& a, const Bucke
 // iterations) are issued together at the start.  The last iteration of a
 // run stores m and x of every pair and sets every flag, so that the dense
 // arrays are complete between runs.
-template <int MODE, int RB>
+// TW (three-weight variant): an unmoved pair is an inactive constraint and
+// sends weight 0, so its dual is 0 (n = z; no storage) and it adds nothing
+// to the partial sums; the tile writes, with each partial, the number of
+// moved pairs in it (the weight of that contribution).  A pair with an
+// entity that no factor weighted takes the three-weight operator.  The
+// last iteration keeps the flags of the moved pairs for the residual pass,
+// which stores z as the m of every other pair (their dual is 0).
+template <int MODE, int RB, bool TW = false>
 __device__ __forceinline__ void xpass_pair_sparse(const XArgs<float>& a, const BucketDesc& b,
                                                   int tile) {
   using PM = PairMap<RB>;
@@ -534,6 +626,7 @@ __device__ __forceinline__ void xpass_pair_sparse(const XArgs<float>& a, const B
   __shared__ float cacc5[NT / 64][CB * 3];
   __shared__ float cnt5[NT / 64][CB];
   __shared__ int any5;
+  __shared__ uint8_t efr[TW ? RB + CB : 1];   // TW: bit 0 centre, bit 1 radius unweighted
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int rg = lane >> 4, cq = lane & 15;
   const int32_t* tiles = a.idx + b.idx_off;
@@ -552,20 +645,26 @@ __device__ __forceinline__ void xpass_pair_sparse(const XArgs<float>& a, const B
     const int l = isrow ? t : t - RB;
     const int e = isrow ? I * RB + l : J * CB + l;
     float zv[3] = {0.f, 0.f, 0.f}, zp[3] = {0.f, 0.f, 0.f};
+    uint8_t fr = 0;
     if (e < b.E) {
       int zc, zr;
       pair_entity(b, ent, e, zc, zr);
       zv[0] = a.z[zc];
       zv[1] = a.z[zc + 1];
       zv[2] = a.z[zr];
-      zp[0] = a.zprev[zc];
-      zp[1] = a.zprev[zc + 1];
-      zp[2] = a.zprev[zr];
+      if constexpr (TW) {
+        fr = (uint8_t)((a.zfree[zc] ? 1 : 0) | (a.zfree[zr] ? 2 : 0));
+      } else {
+        zp[0] = a.zprev[zc];
+        zp[1] = a.zprev[zc + 1];
+        zp[2] = a.zprev[zr];
+      }
     }
+    if constexpr (TW) efr[t] = fr;
 #pragma unroll
     for (int s = 0; s < 3; ++s) {
-      const float u = zp[s] - zv[s];
-      const float n = zv[s] - u;
+      const float u = TW ? 0.f : zp[s] - zv[s];
+      const float n = TW ? zv[s] : zv[s] - u;
       if (isrow) {
         erow[0][l * 3 + s] = zv[s];
         erow[1][l * 3 + s] = n;
@@ -681,7 +780,13 @@ __device__ __forceinline__ void xpass_pair_sparse(const XArgs<float>& a, const B
             v[s] = s < 3 ? rn[s] : cn[c][s - 3];
           }
         }
-        const bool moved = prox_nonoverlap(v);
+        bool moved;
+        if constexpr (TW) {
+          const unsigned fr = (unsigned)efr[li] | ((unsigned)efr[RB + 4 * cq + c] << 2);
+          moved = fr ? prox_nonoverlap_free(v, fr) : prox_nonoverlap(v);
+        } else {
+          moved = prox_nonoverlap(v);
+        }
 #pragma unroll
         for (int s = 0; s < 6; ++s) xo[s][c] = v[s];
         if (moved) {
@@ -707,8 +812,9 @@ __device__ __forceinline__ void xpass_pair_sparse(const XArgs<float>& a, const B
       movedall |= moved_bits << (4 * k);
     }
   }
-  *flagp = (uint16_t)(SAVE ? 0xFFFFu : movedall);
-  // row partials: moved pairs' m plus (valid - moved) * z
+  *flagp = (uint16_t)((SAVE && !TW) ? 0xFFFFu : movedall);
+  // row partials: moved pairs' m plus (valid - moved) * z (TW: moved pairs'
+  // m, with their number as the weight)
   const bool wave_moved = __ballot(movedall != 0) != 0;
 #pragma unroll
   for (int k = 0; k < PRT; ++k) {
@@ -725,7 +831,13 @@ __device__ __forceinline__ void xpass_pair_sparse(const XArgs<float>& a, const B
     }
     if (drow[k] >= 0) {
       const float m = cq == 0 ? ms[0] : (cq == 1 ? ms[1] : ms[2]);
-      a.pool[drow[k]] = fmaf(cnt, erow[0][li * 3 + (cq < 3 ? cq : 0)], m);
+      if constexpr (TW) {
+        const float vc = (float)(hi > lo ? hi - lo : 0);
+        a.pool[drow[k]] = m;
+        a.wc[drow[k]] = vc - cnt;
+      } else {
+        a.pool[drow[k]] = fmaf(cnt, erow[0][li * 3 + (cq < 3 ? cq : 0)], m);
+      }
     }
   }
   // column partials
@@ -756,7 +868,12 @@ __device__ __forceinline__ void xpass_pair_sparse(const XArgs<float>& a, const B
     const int ej = J * CB + t / 3;
     const int rows = ej < b.E ? (ej - I * RB < RB ? ej - I * RB : RB) : 0;
     const float cnt = (float)(rows > 0 ? rows : 0) - mcnt;
-    a.pool[dcol] = fmaf(cnt, ecol[0][t], ms);
+    if constexpr (TW) {
+      a.pool[dcol] = ms;
+      a.wc[dcol] = mcnt;
+    } else {
+      a.pool[dcol] = fmaf(cnt, ecol[0][t], ms);
+    }
   }
 }
 
@@ -1107,14 +1224,95 @@ __device__ __forceinline__ void gen_store(const XArgs<T>& a, const BucketDesc& b
   }
 }
 
+// Three-weight variant of a non-overlap (NS = 6) or wall (NS = 3) factor
+// on arbitrary variables, alpha = 1.  The factor's dual is m - z when it
+// sent weight rho in the last iteration and 0 when it sent weight 0 (its
+// constraint was inactive); edges of variables no factor weighted are
+// received with weight 0.  Each contribution goes out with its weight (m
+// and 1 when the constraint is active, 0 and 0 when not).  The residual
+// pass stores z as the m of inactive factors (dual 0) and marks them
+// active again, so the stored state is explicit between runs.
+template <typename T, int MODE, int NS>
+__device__ __forceinline__ void geom_tw(const XArgs<T>& a, const BucketDesc& b, int64_t f,
+                                        const int (&dims)[4], int arity, T& rmax) {
+  const int64_t nfp = b.nfp;
+  const int32_t* zo = a.idx + b.idx_off;
+  T* M = a.pool + b.m_off;
+  T* X = a.pool + b.x_off;
+  const int32_t* dst = a.idx + b.dst_off;
+  uint8_t* act = a.twb + b.twb_off + f;
+  const bool was = *act != 0;
+  T z[NS], u[NS], v[NS];
+  unsigned fr = 0;
+  int s = 0;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    if (e < arity) {
+      const int z0 = zo[e * nfp + f];
+      if (a.zfree[z0]) fr |= 1u << e;
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        if (c < dims[e]) {
+          z[s] = a.z[z0 + c];
+          ++s;
+        }
+      }
+    }
+  }
+  if constexpr (MODE == PM_RESID) {
+#pragma unroll
+    for (int q = 0; q < NS; ++q) rmax = tmax(rmax, tabs(X[q * nfp + f] - z[q]));
+    if (!was) {
+#pragma unroll
+      for (int q = 0; q < NS; ++q) M[q * nfp + f] = z[q];
+      *act = 1;
+    }
+    return;
+  } else {
+#pragma unroll
+    for (int q = 0; q < NS; ++q) {
+      u[q] = was ? M[q * nfp + f] - z[q] : T(0);
+      v[q] = z[q] - u[q];
+    }
+    bool moved;
+    if constexpr (NS == 6) {
+      moved = fr ? prox_nonoverlap_free(v, fr) : prox_nonoverlap(v);
+    } else {
+      const T* P = a.par + b.par_off;
+      // fr bit 0: the centre edge, bit 1: the radius edge
+      if (fr)
+        moved = prox_wall_free(v, P[f], P[nfp + f], P[2 * nfp + f], fr);
+      else
+        moved = prox_wall(v, P[f], P[nfp + f], P[2 * nfp + f], P[3 * nfp + f]);
+    }
+#pragma unroll
+    for (int q = 0; q < NS; ++q) {
+      const T mn = v[q] + u[q];
+      M[q * nfp + f] = mn;
+      if constexpr (MODE == PM_SAVE) X[q * nfp + f] = v[q];
+      a.pool[dst[q * nfp + f]] = moved ? mn : T(0);
+      a.wc[dst[q * nfp + f]] = moved ? T(1) : T(0);
+    }
+    *act = moved ? 1 : 0;
+  }
+}
+
 // Non-overlap and wall factors on arbitrary variables, and equality
 // factors split into scalar component pairs (App. C: with equal weights
 // both copies take the mean of the pair).
-template <typename T, bool A1, int MODE>
+template <typename T, bool A1, int MODE, bool TW = false>
 __device__ __forceinline__ void xpass_geom(const XArgs<T>& a, const BucketDesc& b, int blk) {
   const int64_t f = (int64_t)blk * NT + threadIdx.x;
   T rmax = T(0);
-  if (f < b.n) {
+  if (TW && f < b.n && b.kind != KD_EQUAL) {
+    if (b.kind == KD_NONOVERLAP) {
+      const int dims[4] = {2, 1, 2, 1};
+      geom_tw<T, MODE, 6>(a, b, f, dims, 4, rmax);
+    } else {
+      const int dims[4] = {2, 1, 0, 0};
+      geom_tw<T, MODE, 3>(a, b, f, dims, 2, rmax);
+    }
+  } else if (f < b.n) {
     if (b.kind == KD_EQUAL) {
       const int dims[4] = {1, 1, 0, 0};
       T u[2], v[2];
@@ -1263,17 +1461,21 @@ enum Features : int {
   FT_WIDE = 8,     // hinge with d <= 64, general hinge, linear dynamics
   FT_PAIRSP = 16,  // dense pair tiles with sparse pair state
   FT_XWIDE = 32,   // hinge and margin with 64 < d < NT (two sweeps, no register arrays)
+  FT_TWA = 64,     // three-weight variant (packing graphs: pair tiles, constraints, slots)
 };
 constexpr int FS_PAIR = FT_PAIR | FT_GEN;
 constexpr int FS_PAIRSP = FT_PAIRSP | FT_GEN;
 constexpr int FS_HINGE = FT_UHINGE | FT_GEN;
 constexpr int FS_ALL = FT_PAIR | FT_UHINGE | FT_GEN | FT_WIDE | FT_PAIRSP;
 constexpr int FS_XW = FT_XWIDE | FT_GEN;
+constexpr int FS_PAIRSP_TW = FT_PAIRSP | FT_GEN | FT_TWA;
+constexpr int FS_GEN_TW = FT_GEN | FT_TWA;
 constexpr int FS_ALLX = FS_ALL | FT_XWIDE;
 
 // One x-pass workgroup's work; blk indexes the x-pass blocks of all buckets.
 template <typename T, bool A1, int MODE, int FS>
 __device__ __forceinline__ void xpass_block(XArgs<T> a, int blk) {
+  constexpr bool TW = (FS & FT_TWA) != 0;
   a.blockmax += blk;
   int bi = 0;
   while (bi + 1 < a.nb && blk >= a.bt[bi].blk1) ++bi;
@@ -1284,21 +1486,21 @@ __device__ __forceinline__ void xpass_block(XArgs<T> a, int blk) {
       if constexpr ((FS & FT_PAIRSP) && MODE != PM_RESID) {
         if (b.sparse) {
           if (b.rb == 16)
-            xpass_pair_sparse<MODE, 16>(a, b, local);
+            xpass_pair_sparse<MODE, 16, TW>(a, b, local);
           else if (b.rb == 32)
-            xpass_pair_sparse<MODE, 32>(a, b, local);
+            xpass_pair_sparse<MODE, 32, TW>(a, b, local);
           else
-            xpass_pair_sparse<MODE, 64>(a, b, local);
+            xpass_pair_sparse<MODE, 64, TW>(a, b, local);
           return;
         }
       }
       if constexpr ((FS & FT_PAIR) || MODE == PM_RESID) {
         if (b.rb == 16)
-          xpass_pair_v4<MODE, 16>(a, b, local);
+          xpass_pair_v4<MODE, 16, TW>(a, b, local);
         else if (b.rb == 32)
-          xpass_pair_v4<MODE, 32>(a, b, local);
+          xpass_pair_v4<MODE, 32, TW>(a, b, local);
         else
-          xpass_pair_v4<MODE, 64>(a, b, local);
+          xpass_pair_v4<MODE, 64, TW>(a, b, local);
       }
     } else {
       if (b.rb == 16)
@@ -1318,7 +1520,7 @@ __device__ __forceinline__ void xpass_block(XArgs<T> a, int blk) {
   } else if ((FS & FT_GEN) && b.mode == BM_GEN_SLOT) {
     xpass_slot<T, A1, MODE>(a, b, local);
   } else if ((FS & FT_GEN) && (b.kind == KD_NONOVERLAP || b.kind == KD_WALL || b.kind == KD_EQUAL)) {
-    xpass_geom<T, A1, MODE>(a, b, local);
+    xpass_geom<T, A1, MODE, TW>(a, b, local);
   } else if ((FS & FT_XWIDE) && (b.kind == KD_HINGE || b.kind == KD_MARGIN) && b.dmax == 0) {
     xpass_hinge_wide<T, A1, MODE, false>(a, b, local);
   } else if (FS & FT_WIDE) {
@@ -1346,8 +1548,174 @@ __global__ __launch_bounds__(NT) void xpass_kernel(XArgs<T> a) {
 constexpr int ZSEG = 16;                  // lanes per medium list
 constexpr int ZPB = NT / ZSEG;            // medium lists per block
 constexpr int ZUN = 8;                    // loads per lane issued at once (medium lists)
+constexpr int ZTU = 16;                   // loads per thread issued at once (transposed)
+
+// Transposed lists (the scalars of pair-tile entities): contribution j of
+// list k at t_base + j * n_t + k.  A block takes L = t_lpb consecutive
+// lists and NT / L threads per list: thread q of a list sums slots
+// j = q, q + NT/L, ... (loads coalesced across the L lists, the first ZTU
+// issued together), and the per-thread sums are added in order of q.  TW:
+// the weights written with the contributions are summed the same way
+// (three-weight variant).
+template <typename T, bool TW>
+__device__ __forceinline__ void zpass_tlist(const ZArgs<T>& a, int blk, T& dmax) {
+  __shared__ T zt[2][NT];
+  const int L = a.t_lpb, nq = NT / L;
+  const int kk = threadIdx.x & (L - 1), q = threadIdx.x / L;
+  const int64_t k = (int64_t)blk * L + kk;
+  const bool ok = k < a.n_t;
+  T num = T(0), den = T(0);
+  if (ok) {
+    const T* p = a.pool + a.t_base + k;
+    const T* w = TW ? a.wc + a.t_base + k : (a.wz ? a.wz + a.t_base + k : nullptr);
+    T v[ZTU], c[ZTU];
+#pragma unroll
+    for (int i = 0; i < ZTU; ++i) {
+      const int j = q + nq * i;
+      v[i] = T(0);
+      c[i] = T(0);
+      if (j < a.t_len) {
+        v[i] = p[(int64_t)j * a.n_t];
+        if (TW || w) c[i] = w[(int64_t)j * a.n_t];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < ZTU; ++i) {
+      if (TW) {
+        num += v[i];
+        den += c[i];
+      } else {
+        num += w ? c[i] * v[i] : v[i];
+      }
+    }
+    for (int j = q + nq * ZTU; j < a.t_len; j += nq) {
+      const T vj = p[(int64_t)j * a.n_t];
+      if (TW) {
+        num += vj;
+        den += w[(int64_t)j * a.n_t];
+      } else {
+        num += w ? w[(int64_t)j * a.n_t] * vj : vj;
+      }
+    }
+  }
+  zt[0][threadIdx.x] = num;
+  zt[1][threadIdx.x] = den;
+  __syncthreads();
+  if (ok && q == 0) {
+    T tn = zt[0][kk], td = zt[1][kk];
+    for (int i = 1; i < nq; ++i) {
+      tn += zt[0][i * L + kk];
+      td += zt[1][i * L + kk];
+    }
+    const int zi = a.var_t[k];
+    T zn = a.zin[zi];
+    if (TW) {
+      if (td > T(0)) zn = tn / td;
+      a.zfree[zi] = td > T(0) ? 0 : 1;
+    } else {
+      zn = tn / a.deg_t[k];
+    }
+    a.zout[zi] = zn;
+    if (a.check) dmax = tabs(zn - a.zin[zi]) * ((!TW && a.rmz) ? a.rmz[zi] : T(1));
+  }
+}
+// Three-weight variant: z_b = (sum of the contributions) / (sum of the
+// weights written with them), over the same lists in the same order; when
+// the weights sum to 0 no factor weighted b, z_b keeps its value and zfree
+// marks b for the next x-update.
+template <typename T>
+__device__ __forceinline__ void zpass_block_tw(ZArgs<T> a, int blk) {
+  __shared__ T zr2[2][NT / 64];
+  T dmax = T(0);
+  if (blk < a.nb_t) {
+    zpass_tlist<T, true>(a, blk, dmax);
+    if (a.check) block_max_store(dmax, a.blockmax + blk);
+    return;
+  }
+  a.blockmax += a.nb_t;
+  blk -= a.nb_t;
+  auto finish = [&](int zi, T num, T den) {
+    T zn = a.zin[zi];
+    if (den > T(0)) zn = num / den;
+    a.zout[zi] = zn;
+    a.zfree[zi] = den > T(0) ? 0 : 1;
+    if (a.check) dmax = tabs(zn - a.zin[zi]);
+  };
+  if (blk < a.n_b) {
+    const int64_t o1 = a.rng_b[2 * blk + 1];
+    T num = T(0), den = T(0);
+    for (int64_t j = a.rng_b[2 * blk] + threadIdx.x; j < o1; j += NT) {
+      num += a.pool[j];
+      den += a.wc[j];
+    }
+    num = admmi::wave_sum(num);
+    den = admmi::wave_sum(den);
+    if ((threadIdx.x & 63) == 0) {
+      zr2[0][threadIdx.x >> 6] = num;
+      zr2[1][threadIdx.x >> 6] = den;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      T tn = zr2[0][0], td = zr2[1][0];
+#pragma unroll
+      for (int q = 1; q < NT / 64; ++q) {
+        tn += zr2[0][q];
+        td += zr2[1][q];
+      }
+      finish(a.var_b[blk], tn, td);
+    }
+  } else if (blk < a.n_b + a.nb_w) {
+    const int sl = threadIdx.x & (ZSEG - 1);
+    const int64_t k = (int64_t)(blk - a.n_b) * ZPB + (threadIdx.x / ZSEG);
+    const bool ok = k < a.n_w;
+    T num = T(0), den = T(0);
+    if (ok) {
+      int64_t j0, j1;
+      if (a.w_stride) {
+        j0 = a.w_base + k * a.w_stride;
+        j1 = j0 + a.w_stride;
+      } else {
+        j0 = a.rng_w[2 * k];
+        j1 = a.rng_w[2 * k + 1];
+      }
+      for (int64_t j = j0 + sl; j < j1; j += ZSEG) {
+        num += a.pool[j];
+        den += a.wc[j];
+      }
+    }
+    num = admmi::row16_sum(num);
+    den = admmi::row16_sum(den);
+    if (ok && sl == 0) finish(a.var_w[k], num, den);
+  } else {
+    const int64_t k = (int64_t)(blk - a.n_b - a.nb_w) * NT + threadIdx.x;
+    if (k < a.n_l) {
+      const int64_t o = a.l_base + k * LANE_MAX;
+      T num = a.pool[o], den = a.wc[o];
+#pragma unroll
+      for (int j = 1; j < LANE_MAX; ++j) {
+        num += a.pool[o + j];
+        den += a.wc[o + j];
+      }
+      finish(a.var_l[k], num, den);
+    }
+  }
+  if (a.check) block_max_store(dmax, a.blockmax + blk);
+}
+
 template <typename T>
 __device__ __forceinline__ void zpass_block(ZArgs<T> a, int blk) {
+  if (a.wc) {
+    zpass_block_tw(a, blk);
+    return;
+  }
+  if (blk < a.nb_t) {
+    T dt = T(0);
+    zpass_tlist<T, false>(a, blk, dt);
+    if (a.check) block_max_store(dt, a.blockmax + blk);
+    return;
+  }
+  a.blockmax += a.nb_t;
+  blk -= a.nb_t;
   __shared__ T zred[NT / 64];
   a.blockmax += blk;
   T dmax = T(0);

@@ -22,6 +22,14 @@ struct Plan {
   std::vector<int32_t> var_b, var_w, var_l;   // z lists: long, medium, short
   std::vector<int64_t> rng_b, rng_w;
   std::vector<double> deg_b, deg_w, deg_l;  // per z list: sum of its edges' rho / graph rho
+  // Transposed lists of the scalars of pair-tile entities (64-row tiles):
+  // contribution j of list k at t_base + j * n_t + k, so that the 192
+  // partials a tile writes for one entity block are contiguous.
+  std::vector<int32_t> var_t;
+  std::vector<double> deg_t;
+  int64_t t_base = 0;
+  int32_t t_len = 0;
+  int32_t t_lpb = 32;           // transposed lists per z-pass block
   bool weighted = false;        // groups with different rho: weighted z-sums
   std::vector<double> wz;       // weighted: relative rho of every contribution position
   std::vector<double> rmz;      // weighted: per z scalar, the largest rho of its edges
@@ -40,6 +48,7 @@ struct Plan {
 
 struct EngineBase {
   int32_t graph_block = 0;  // graph driver: iterations per recorded block (0: launches)
+  bool twa = false;         // three-weight variant (set before upload)
   virtual ~EngineBase() {}
   // Whether the resident driver can run this plan on the device (LDS image
   // plus the kernel's static LDS within the per-workgroup limit).

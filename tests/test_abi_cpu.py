@@ -260,3 +260,23 @@ def test_mpc_batch_validation_before_device():
     _expect(A.E_ARG, M.MPCBatch, [neg])
     ok = W.MPCInstance(10, 4, 2, A_, B_, np.zeros(4), np.ones(4), np.ones(2), 1.0)
     _expect(A.E_ARG, M.MPCBatch, [ok], -1.0)
+
+
+def test_three_weight_validation():
+    """The three-weight variant is validated before any device call: packing
+    graphs pass (pair tiles with the sparse state in FP32, the general layout
+    in FP64 or with the dense pair state), other graphs, alpha != 1 and the
+    resident driver are refused."""
+    p = W.workload("packing_tri10")
+    for prec, dense, tiles in ((A.FP32, False, True), (A.FP64, False, False), (A.FP32, True, False)):
+        g = A.Graph.from_problem(p, precision=prec, device=None, three_weight=True,
+                                 pair_state=A.PAIR_STATE_DENSE if dense else A.PAIR_STATE_AUTO)
+        assert _finalize_cpu(g) in (A.OK, A.E_NO_DEVICE)
+        inf = g.info()
+        assert inf["three_weight"] == 1 and (inf["n_pair_tiles"] > 0) == tiles
+        assert inf["driver"] == A.DRIVER_GRAPH
+    for q, kw in ((W.svm(300, 3, seed=1), {}), (p, dict(alpha=1.5)),
+                  (p, dict(driver=A.DRIVER_RESIDENT))):
+        g = A.Graph.from_problem(q, device=None, three_weight=True, **kw)
+        assert _finalize_cpu(g) == A.E_UNSUPPORTED
+    _expect(A.E_ARG, A.Graph([1]).set_option, A.OPT_THREE_WEIGHT, 2)
