@@ -194,6 +194,70 @@ def bench_mpc_batch(torch):
                                     plan=dict(zip(("pack1", "order", "grid"), plans[k3]))))
 
 
+def packing_violation(problem, z):
+    """Largest violation of any packing constraint at z (overlap of two
+    disks, a disk beyond a wall, a negative radius): a measurement of the
+    returned z, computed here in FP64 from the problem's data."""
+    import numpy as np
+    z = np.asarray(z, dtype=np.float64)
+    c = np.stack([z[0::3], z[1::3]], axis=1)
+    r = z[2::3]
+    worst = float(np.max(-r, initial=0.0))
+    for Q, V in problem.meta["walls"]:
+        worst = max(worst, float(np.max(r - ((c[:, 0] - V[0]) * Q[0] + (c[:, 1] - V[1]) * Q[1]),
+                                        initial=0.0)))
+    n = len(r)
+    for i0 in range(0, n, 256):
+        ci, ri = c[i0:i0 + 256], r[i0:i0 + 256]
+        d = np.sqrt(((ci[:, None, :] - c[None, :, :]) ** 2).sum(-1))
+        ov = ri[:, None] + r[None, :] - d
+        ii = np.arange(i0, i0 + len(ri))[:, None]
+        ov[ii >= np.arange(n)[None, :]] = 0.0
+        worst = max(worst, float(ov.max(initial=0.0)))
+    return worst
+
+
+def bench_three_weight(torch, stream):
+    """The three-weight variant against Algorithm 2 on the 10-disk triangle
+    and the 2000-disk square: iterations until the largest constraint
+    violation of z falls below a threshold (checked every `every`
+    iterations), the violation and area after a fixed count, and seconds
+    per iteration of a 1000-iteration solve from z0 (both on the graph
+    driver)."""
+    import numpy as np
+    import workloads as W
+    from paper_1603_02526_amd import admm as A
+    out = {}
+    for name, thr, cap, every in (("packing_tri10", 1e-6, 20000, 50),
+                                  ("packing_sq2000", 1e-3, 6000, 100)):
+        p = W.workload(name)
+        row = {}
+        for key, twa in (("plain", False), ("three_weight", True)):
+            g = A.Graph.from_problem(p, precision=A.FP32, device=0, three_weight=twa,
+                                     driver=A.DRIVER_GRAPH)
+            sec = time_solve(g, p.z0, 1000, 3, 1, torch, stream)
+            g.set_state(p.z0)
+            g.run(1000, stream)
+            z = g.z(stream)
+            res = dict(s_per_iteration=sec / 1000, violation_at_1000=packing_violation(p, z),
+                       area_at_1000=float(np.pi * np.sum(z[2::3] ** 2)))
+            g.set_state(p.z0)
+            it, hit = 0, None
+            while it < cap:
+                g.run(every, stream)
+                it += every
+                if packing_violation(p, g.z(stream)) < thr:
+                    hit = it
+                    break
+            res["iterations_to_violation_below"] = hit
+            res["threshold"] = thr
+            res["checked_every"] = every
+            row[key] = res
+            del g
+        out[name] = row
+    return out
+
+
 def mpc_flops_per_iteration(T, n, m):
     """Arithmetic of one ADMM iteration of one MPC instance (FMA = 2): the
     dynamics projection of every step (v = S(Ma - b), a -= M^T v, b += v),
@@ -586,6 +650,9 @@ def main():
                                     pair_state="dense" if not inff["sparse_pair_state"] else "sparse")
         del gf
         out["secondary"] = secd
+
+    if not args.no_secondary:
+        out["secondary"]["three_weight"] = bench_three_weight(torch, stream)
 
     if not args.no_mpc:
         out.setdefault("secondary", {})["mpc_batch_4096"] = bench_mpc_batch(torch)
