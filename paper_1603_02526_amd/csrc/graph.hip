@@ -463,7 +463,9 @@ admm_status build_plan(admm_graph& g, Plan& P, bool no_tiles) {
         par[(d + 2) * b.nfp + f] = rg / (aa + 1.0);
       }
       P.n_m += (int64_t)gr.arity * b.nfp;
-      const int64_t tiles = (gr.n + NT - 1) / NT;
+      // d <= 32: two lanes per factor, NT / 2 factors per workgroup
+      const int64_t fpb = b.dmax == 32 ? NT / 2 : NT;
+      const int64_t tiles = (gr.n + fpb - 1) / fpb;
       b.dst_off = (int64_t)P.idx.size();
       P.idx.resize(P.idx.size() + tiles * gr.arity, -1);
       b.blk0 = (int32_t)blocks;

@@ -1005,6 +1005,139 @@ __device__ __forceinline__ void xpass_hinge(const XArgs<T>& a, const BucketDesc&
   }
 }
 
+// Hinge factors sharing one variable list with d <= 32 (the SVM): two lanes
+// per factor, NT / 2 factors per workgroup, so twice as many wavefronts
+// keep loads in flight.  Lane h of a pair takes components [h dh, (h+1) dh)
+// (dh = ceil(d / 2)) and lane 1 also the b edge; both lanes form the same
+// dot product (partial sums exchanged, added in the same order) and step.
+// Every component's m is summed over the workgroup's factors: over the
+// lanes of one parity of a wavefront (xor butterfly over lane bits 1..5),
+// then over the four wavefronts in order.
+template <typename T>
+__device__ __forceinline__ T sum_parity_row(T v);
+
+// Sum over the lanes of one parity within each 16-lane row (lane bits 1..3),
+// DPP only; every lane returns its row's sum for its parity.
+template <>
+__device__ __forceinline__ float sum_parity_row<float>(float v) {
+  v += ADMM_DPP(v, 0x4E, 0xF);    // quad_perm [2,3,0,1]: lanes i, i ^ 2
+  v += ADMM_DPP(v, 0x124, 0xF);   // row_ror:4
+  v += ADMM_DPP(v, 0x128, 0xF);   // row_ror:8
+  return v;
+}
+
+template <>
+__device__ __forceinline__ double sum_parity_row<double>(double v) {
+#pragma unroll
+  for (int o = 2; o < 16; o <<= 1) v += __shfl_xor(v, o, 16);
+  return v;
+}
+
+template <typename T, bool A1, int MODE>
+__device__ __forceinline__ void xpass_hinge2(const XArgs<T>& a, const BucketDesc& b, int blk) {
+  constexpr int DH = 16;
+  constexpr int FPB = NT / 2;
+  __shared__ T wsum2[NT / 16][33];   // per 16-lane row, per component
+  __shared__ T zsh[33];              // z of the bucket's d + 1 variables
+  const int t = threadIdx.x, lane = t & 63, h = t & 1, row = t >> 4;
+  const int d = b.d, dh = (d + 1) / 2;
+  const int64_t f = (int64_t)blk * FPB + (t >> 1);
+  const bool valid = f < b.n;
+  const int64_t ff = valid ? f : 0;
+  const int64_t nfp = b.nfp;
+  const int32_t* zo = a.idx + b.idx_off;
+  const T* P = a.par + b.par_off;
+  T* M = a.pool + b.m_off;
+  T* X = a.pool + b.x_off;
+  const T alpha = (T)b.alpha;
+  const int k0 = h ? dh : 0, k1 = h ? d : dh;
+  if (t <= d) zsh[t] = a.z[zo[t]];
+  // every load of the factor first (a valid component index everywhere,
+  // k0 <= d, so no load sits behind a branch), then the arithmetic
+  T mv[DH], pv[DH], xv[DH];
+#pragma unroll
+  for (int i = 0; i < DH; ++i) {
+    const int kc = k0 + i < k1 ? k0 + i : k0;
+    mv[i] = M[kc * nfp + ff];
+    pv[i] = MODE == PM_RESID ? T(0) : P[kc * nfp + ff];
+    xv[i] = (!A1 || MODE == PM_RESID) ? X[kc * nfp + ff] : T(0);
+  }
+  const T mb = M[d * nfp + ff];
+  const T xob = (!A1 || MODE == PM_RESID) ? X[d * nfp + ff] : T(0);
+  T y = T(0), C = T(0), iD = T(0);
+  if constexpr (MODE != PM_RESID) {
+    y = P[d * nfp + ff];
+    C = P[(d + 1) * nfp + ff];
+    iD = P[(d + 2) * nfp + ff];
+  }
+  __syncthreads();
+  const T zb = zsh[d];
+  if constexpr (MODE == PM_RESID) {
+    T rmax = T(0);
+#pragma unroll
+    for (int i = 0; i < DH; ++i) {
+      const int k = k0 + i;
+      if (valid && k < k1) rmax = tmax(rmax, tabs(xv[i] - zsh[k]));
+    }
+    if (valid && h) rmax = tmax(rmax, tabs(xob - zb));
+    block_max_store(rmax, a.blockmax);
+    return;
+  } else {
+    T uv[DH], nv[DH];
+    T dot = T(0);
+#pragma unroll
+    for (int i = 0; i < DH; ++i) {
+      const int k = k0 + i;
+      const bool on = k < k1;
+      state_un<T, A1>(mv[i], xv[i], zsh[on ? k : k0], alpha, uv[i], nv[i]);
+      if (on) dot += nv[i] * pv[i];
+    }
+    T ub = T(0), nb = T(0);
+    state_un<T, A1>(mb, xob, zb, alpha, ub, nb);
+    if (!h) ub = nb = T(0);
+    // both lanes: (even partial + odd partial) + y nb, the same bits in each
+    const T other = __shfl_xor(dot, 1, 64);
+    const T nbb = __shfl_xor(nb, 1, 64);
+    const T full = (h ? other + dot : dot + other) + y * (h ? nb : nbb);
+    const T tau = tmin(C, tmax(T(0), (T(1) - full) * iD));
+    const T st = tau * (T)b.irho;
+    T mnb = T(0);
+    if (h) {
+      const T xb = nb + st * y;
+      mnb = xb + ub;
+      if (valid) {
+        M[d * nfp + ff] = mnb;
+        if constexpr (!A1 || MODE == PM_SAVE) X[d * nfp + ff] = xb;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < DH; ++i) {   // i < dh is uniform: every lane takes part
+      if (i >= dh) break;
+      const int k = k0 + i;
+      const bool on = k < k1;
+      const T xk = nv[i] + st * pv[i];
+      const T mn = xk + uv[i];
+      if (valid && on) {
+        M[k * nfp + ff] = mn;
+        if constexpr (!A1 || MODE == PM_SAVE) X[k * nfp + ff] = xk;
+      }
+      const T s = sum_parity_row<T>((valid && on) ? mn : T(0));
+      if ((lane & 15) < 2 && on) wsum2[row][k] = s;
+    }
+    {
+      const T s = sum_parity_row<T>((valid && h) ? mnb : T(0));
+      if ((lane & 15) == 1) wsum2[row][d] = s;
+    }
+    __syncthreads();
+    if (t <= d) {
+      T acc = wsum2[0][t];
+#pragma unroll
+      for (int q = 1; q < NT / 16; ++q) acc += wsum2[q][t];
+      a.pool[a.idx[b.dst_off + (int64_t)blk * (d + 1) + t]] = acc;
+    }
+  }
+}
+
 // Hinge and margin factors with d > 64 weight components (up to NT - 1):
 // the same operator as xpass_hinge without register arrays.  A first sweep
 // over the components forms the dot product s = y(n_w.a + n_b) (+ n_xi);
@@ -1512,7 +1645,7 @@ __device__ __forceinline__ void xpass_block(XArgs<T> a, int blk) {
     }
   } else if ((FS & (FT_UHINGE | FT_WIDE | FT_XWIDE)) && b.mode == BM_UNIF_HINGE) {
     if ((FS & FT_UHINGE) && b.dmax == 32)
-      xpass_hinge<T, A1, MODE, true, 32>(a, b, local);
+      xpass_hinge2<T, A1, MODE>(a, b, local);
     else if ((FS & FT_WIDE) && b.dmax == 64)
       xpass_hinge<T, A1, MODE, true, 64>(a, b, local);
     else if ((FS & FT_XWIDE) && b.dmax == 0)

@@ -1,6 +1,6 @@
 // Small MLP for the learned MPC warm start: y = W3 relu(W2 relu(W1 x + b1) +
 // b2) + b3, mean-squared-error loss, Adam.  Every matrix product runs on the
-// gfx950 matrix cores (v_mfma_f32_16x16x16bf16_1k): operands rounded to
+// gfx950 matrix cores (v_mfma_f32_16x16x32_bf16): operands rounded to
 // bf16 (round to nearest even) while staged through LDS, products
 // accumulated in fp32.  Master weights, activations and gradients are fp32
 // in device memory.  Bias, ReLU and the ReLU mask of the backward pass are
@@ -18,7 +18,8 @@
 
 namespace {
 
-typedef short v4s __attribute__((ext_vector_type(4)));
+typedef short v8s __attribute__((ext_vector_type(8)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
 constexpr int GT = 256;  // threads per GEMM workgroup (4 wavefronts)
@@ -36,8 +37,9 @@ enum Epi : int { EPI_PLAIN = 0, EPI_BIAS = 1, EPI_BIAS_RELU = 2, EPI_MASK = 3, E
 // C[M x N] = sum_k A(m,k) B(k,n); A(m,k) = TA ? A[k*lda+m] : A[m*lda+k],
 // B(k,n) = TB ? B[n*ldb+k] : B[k*ldb+n].  Epilogue per EPI.
 // Workgroup tile 64 x 64, each wavefront a 32 x 32 quarter as 2 x 2 MFMA
-// tiles of 16 x 16, K consumed 32 at a time through LDS (two MFMA steps per
-// barrier).  Split K: workgroup z covers K range [z*kc, (z+1)*kc) and
+// tiles of 16 x 16, K consumed 32 at a time through LDS: one gfx950
+// v_mfma_f32_16x16x32_bf16 per tile and barrier (lane l holds row or
+// column l % 16 and the eight k = 8 (l / 16) .. + 7 of the step).  Split K: workgroup z covers K range [z*kc, (z+1)*kc) and
 // writes its partial product to C + z*M*N (plain epilogue only).
 template <bool TA, bool TB, int EPI>
 __global__ __launch_bounds__(GT) void gemm_kernel(int M, int N, int K, int kc,
@@ -102,26 +104,27 @@ __global__ __launch_bounds__(GT) void gemm_kernel(int M, int N, int K, int kc,
     __syncthreads();
     if (k0 + BK < kend) load_tile(k0 + BK);
 #pragma unroll
-    for (int kk = 0; kk < BK; kk += 16) {
-      const int kq = kk + (lane >> 4) * 4;
-      v4s af[2], bf[2];
+    for (int kk = 0; kk < BK; kk += 32) {
+      const int kq = kk + (lane >> 4) * 8;
+      v8s af[2], bf[2];
 #pragma unroll
       for (int i = 0; i < 2; ++i) {
         const int row = wm + i * 16 + (lane & 15);
 #pragma unroll
-        for (int j = 0; j < 4; ++j) af[i][j] = (short)As[row][kq + j];
+        for (int j = 0; j < 8; ++j) af[i][j] = (short)As[row][kq + j];
       }
 #pragma unroll
       for (int i = 0; i < 2; ++i) {
         const int col = wn + i * 16 + (lane & 15);
 #pragma unroll
-        for (int j = 0; j < 4; ++j) bf[i][j] = (short)Bs[kq + j][col];
+        for (int j = 0; j < 8; ++j) bf[i][j] = (short)Bs[kq + j][col];
       }
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[i], bf[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+              __builtin_bit_cast(v8bf, af[i]), __builtin_bit_cast(v8bf, bf[j]), acc[i][j], 0, 0, 0);
     }
     __syncthreads();
   }
