@@ -45,6 +45,7 @@ int64_t resident_image_bytes(const Plan& P, int64_t nz, int64_t es) {
   b += r16((int64_t)P.var_b.size() * 4) + r16((int64_t)P.rng_b.size() * 8) + r16((int64_t)P.deg_b.size() * es);
   b += r16((int64_t)P.var_w.size() * 4) + r16((int64_t)P.rng_w.size() * 8) + r16((int64_t)P.deg_w.size() * es);
   b += r16((int64_t)P.var_l.size() * 4) + r16((int64_t)P.deg_l.size() * es);
+  b += r16((int64_t)P.bt.size() * (int64_t)sizeof(BucketDesc));
   return b;
 }
 

@@ -149,6 +149,7 @@ struct Engine : EngineBase {
     r.o_deg_w = add(deg_w, nullptr, n_w * es);
     r.o_var_l = add(var_l, nullptr, n_l * 4);
     r.o_deg_l = add(deg_l, nullptr, n_l * es);
+    r.o_bt = add(bt, nullptr, (int64_t)nb * (int64_t)sizeof(BucketDesc));
     r.xblocks = (int32_t)xblocks;
     r.zblocks = (int32_t)zblocks;
     r.z_words = (int32_t)(nz * es / 4);

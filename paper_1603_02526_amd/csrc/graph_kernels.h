@@ -1949,7 +1949,7 @@ __global__ __launch_bounds__(NT) void zpass_kernel(ZArgs<T> a) {
 // are copied into LDS at the start, the x-pass and z-pass blocks run one
 // after another with workgroup barriers in between (the order that separate
 // launches would impose), and the pool and the final z are copied back.
-// Bucket descriptors stay in global memory.  Pair tiles are not used here.
+// The bucket table is staged in LDS too.  Pair tiles are not used here.
 // ---------------------------------------------------------------------------
 constexpr int RES_MAX_REG = 16;
 constexpr int FS_RES = FT_UHINGE | FT_GEN | FT_WIDE | FT_XWIDE;
@@ -1967,6 +1967,7 @@ struct ResArgs {
   int32_t nreg;
   int32_t o_pool, o_par, o_idx, o_z0, o_z1;
   int32_t o_var_b, o_rng_b, o_deg_b, o_var_w, o_rng_w, o_deg_w, o_var_l, o_deg_l;
+  int32_t o_bt;     // the bucket table
   int32_t zc, iters, xblocks, zblocks, z_words;
   T* z_back[2];     // global z buffers (the final z is copied to z_back[final index])
 };
@@ -1983,6 +1984,7 @@ __global__ __launch_bounds__(NT) void resident_kernel(XArgs<T> xa, ZArgs<T> za, 
   xa.pool = (T*)(lds_img + r.o_pool);
   xa.par = (const T*)(lds_img + r.o_par);
   xa.idx = (const int32_t*)(lds_img + r.o_idx);
+  xa.bt = (const BucketDesc*)(lds_img + r.o_bt);
   za.pool = xa.pool;
   za.var_b = (const int32_t*)(lds_img + r.o_var_b);
   za.rng_b = (const int64_t*)(lds_img + r.o_rng_b);
