@@ -174,6 +174,9 @@ struct Engine : EngineBase {
         if (b.mode == BM_PAIR) need |= b.sparse ? FT_PAIRSP : FT_PAIR;
         else if ((b.kind == KD_HINGE || b.kind == KD_MARGIN) && b.dmax == 0) need |= FT_XWIDE;
         else if (b.mode == BM_UNIF_HINGE && b.dmax == 32) need |= FT_UHINGE;
+        else if ((b.mode == BM_UNIF_HINGE || b.kind == KD_HINGE || b.kind == KD_MARGIN) &&
+                 b.dmax == 64)
+          need |= FT_W64;
         else if (b.mode == BM_GEN_SLOT || b.kind == KD_NONOVERLAP || b.kind == KD_WALL ||
                  b.kind == KD_EQUAL)
           need |= FT_GEN;
@@ -184,6 +187,7 @@ struct Engine : EngineBase {
            : ((need & ~FS_PAIR) == 0)   ? FS_PAIR
            : ((need & ~FS_PAIRSP) == 0) ? FS_PAIRSP
            : ((need & ~FS_HINGE) == 0)  ? FS_HINGE
+           : ((need & ~FS_WIDE) == 0)   ? FS_WIDE
            : ((need & ~FS_XW) == 0)     ? FS_XW
            : ((need & ~FS_ALL) == 0)    ? FS_ALL
                                         : FS_ALLX;
@@ -342,6 +346,7 @@ struct Engine : EngineBase {
     if (fs == FS_PAIR) launch_x_fs<A1, FS_PAIR>(mode, st, e0, e1);
     else if (fs == FS_PAIRSP) launch_x_fs<A1, FS_PAIRSP>(mode, st, e0, e1);
     else if (fs == FS_HINGE) launch_x_fs<A1, FS_HINGE>(mode, st, e0, e1);
+    else if (fs == FS_WIDE) launch_x_fs<A1, FS_WIDE>(mode, st, e0, e1);
     else if (fs == FS_XW) launch_x_fs<A1, FS_XW>(mode, st, e0, e1);
     else if (fs == FS_ALL) launch_x_fs<A1, FS_ALL>(mode, st, e0, e1);
     else if (fs == FS_ALLX) launch_x_fs<A1, FS_ALLX>(mode, st, e0, e1);

@@ -260,6 +260,7 @@ __device__ __forceinline__ bool prox_wall_free(T* v, T qx, T qy, T qv, unsigned 
 // columns in registers and then across the four wavefronts.
 // Partials per tile: [row li][3] (RB rows) then [col lj][3] (64 columns).
 // ---------------------------------------------------------------------------
+constexpr int PAIR_UNROLL_F64 = 4;   // FP64 pair rows per unrolled step
 template <typename T, bool A1, int MODE, int RB>
 __device__ __forceinline__ void xpass_pair(const XArgs<T>& a, const BucketDesc& b, int tile) {
   constexpr int CB = PB;              // columns per tile
@@ -298,7 +299,10 @@ __device__ __forceinline__ void xpass_pair(const XArgs<T>& a, const BucketDesc& 
   T ca0 = T(0), ca1 = T(0), ca2 = T(0);
   T rv0 = T(0), rv1 = T(0), rv2 = T(0);
   T rmax = T(0);
-#pragma unroll
+  // FP64: rows four at a time, so that the loads in flight stay within the
+  // registers of four wavefronts per SIMD
+  constexpr int UNR = sizeof(T) == 8 ? PAIR_UNROLL_F64 : PRR;
+#pragma unroll UNR
   for (int k = 0; k < PRR; ++k) {
     const int li = w * PRR + k;
     const int ei = I * RB + li;
@@ -721,13 +725,10 @@ __device__ __forceinline__ void xpass_pair_sparse(const XArgs<float>& a, const B
   }
   float* mt = a.pool + b.m_off + (int64_t)tile * TS;
   float* xt = a.pool + b.x_off + (int64_t)tile * TS;
-  float rs[PRT][3], rmc[PRT], cs[4][3], cmc[4];
-#pragma unroll
-  for (int k = 0; k < PRT; ++k) {
-    rmc[k] = 0.f;
-#pragma unroll
-    for (int s = 0; s < 3; ++s) rs[k][s] = 0.f;
-  }
+  // One row of the thread at a time, its partial emitted before the next
+  // row starts, so that only the column sums live across rows (register
+  // pressure sets how many workgroups share a CU).
+  float cs[4][3], cmc[4];
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
     cmc[c] = 0.f;
@@ -735,18 +736,21 @@ __device__ __forceinline__ void xpass_pair_sparse(const XArgs<float>& a, const B
     for (int s = 0; s < 3; ++s) cs[c][s] = 0.f;
   }
   uint32_t movedall = 0;
-  if (work) {
+  bool wave_moved = false;
 #pragma unroll
-    for (int k = 0; k < PRT; ++k) {
-      const uint32_t rowwork = (work >> (4 * k)) & 0xFu;
-      if (!rowwork) continue;
-      const int li = PM::row(w, k, rg);
+  for (int k = 0; k < PRT; ++k) {
+    const int li = PM::row(w, k, rg);
+    const uint32_t rowwork = (work >> (4 * k)) & 0xFu;
+    float rs[3] = {0.f, 0.f, 0.f}, rmc = 0.f;
+    uint32_t moved_bits = 0;
+    if (rowwork) {
       const uint32_t rowbits = (fl >> (4 * k)) & 0xFu;
-      f4v mv[6];
+      // mo: the row's m, read where stored and overwritten column by column
+      f4v mo[6];
       if (rowbits) {
 #pragma unroll
         for (int s = 0; s < 6; ++s)
-          mv[s] = *(const f4v*)(mt + s * TSZ + li * CB + 4 * cq);
+          mo[s] = *(const f4v*)(mt + s * TSZ + li * CB + 4 * cq);
       }
       float rz[3], rn[3], ru[3];
 #pragma unroll
@@ -755,26 +759,28 @@ __device__ __forceinline__ void xpass_pair_sparse(const XArgs<float>& a, const B
         rn[s] = erow[1][li * 3 + s];
         ru[s] = erow[2][li * 3 + s];
       }
-      f4v mo[6], xo[6];
-#pragma unroll
-      for (int c = 0; c < 4; ++c)
-#pragma unroll
-        for (int s = 0; s < 6; ++s) {
-          mo[s][c] = s < 3 ? rz[s] : cz[c][s - 3];
-          xo[s][c] = s < 3 ? rn[s] : cn[c][s - 3];
-        }
-      uint32_t moved_bits = 0;
+      f4v xo[6];
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
-        if (!((rowwork >> c) & 1u)) continue;
+        float zv[6];
+#pragma unroll
+        for (int s = 0; s < 6; ++s) zv[s] = s < 3 ? rz[s] : cz[c][s - 3];
+        if (!((rowwork >> c) & 1u)) {
+          // not a factor of this iteration's work: m = z, x = n
+#pragma unroll
+          for (int s = 0; s < 6; ++s) {
+            mo[s][c] = zv[s];
+            if constexpr (SAVE) xo[s][c] = s < 3 ? rn[s] : cn[c][s - 3];
+          }
+          continue;
+        }
         const bool expl = (rowbits >> c) & 1u;
         float u[6], v[6];
 #pragma unroll
         for (int s = 0; s < 6; ++s) {
           if (expl) {
-            const float zv = s < 3 ? rz[s] : cz[c][s - 3];
-            u[s] = mv[s][c] - zv;
-            v[s] = zv - u[s];
+            u[s] = mo[s][c] - zv[s];
+            v[s] = zv[s] - u[s];
           } else {
             u[s] = s < 3 ? ru[s] : ecol[2][(4 * cq + c) * 3 + s - 3];
             v[s] = s < 3 ? rn[s] : cn[c][s - 3];
@@ -787,19 +793,24 @@ __device__ __forceinline__ void xpass_pair_sparse(const XArgs<float>& a, const B
         } else {
           moved = prox_nonoverlap(v);
         }
+        if constexpr (SAVE) {
 #pragma unroll
-        for (int s = 0; s < 6; ++s) xo[s][c] = v[s];
+          for (int s = 0; s < 6; ++s) xo[s][c] = v[s];
+        }
         if (moved) {
           moved_bits |= 1u << c;
 #pragma unroll
           for (int s = 0; s < 6; ++s) mo[s][c] = v[s] + u[s];
 #pragma unroll
           for (int s = 0; s < 3; ++s) {
-            rs[k][s] += mo[s][c];
+            rs[s] += mo[s][c];
             cs[c][s] += mo[s + 3][c];
           }
-          rmc[k] += 1.f;
+          rmc += 1.f;
           cmc[c] += 1.f;
+        } else {
+#pragma unroll
+          for (int s = 0; s < 6; ++s) mo[s][c] = zv[s];
         }
       }
       if (SAVE || moved_bits) {
@@ -809,25 +820,22 @@ __device__ __forceinline__ void xpass_pair_sparse(const XArgs<float>& a, const B
           if constexpr (SAVE) *(f4v*)(xt + s * TSZ + li * CB + 4 * cq) = xo[s];
         }
       }
-      movedall |= moved_bits << (4 * k);
     }
-  }
-  *flagp = (uint16_t)((SAVE && !TW) ? 0xFFFFu : movedall);
-  // row partials: moved pairs' m plus (valid - moved) * z (TW: moved pairs'
-  // m, with their number as the weight)
-  const bool wave_moved = __ballot(movedall != 0) != 0;
-#pragma unroll
-  for (int k = 0; k < PRT; ++k) {
-    const int li = PM::row(w, k, rg);
+    movedall |= moved_bits << (4 * k);
+    // row partial: moved pairs' m plus (valid - moved) * z (TW: moved
+    // pairs' m, with their number as the weight); the DPP sums are skipped
+    // when no pair of the row's wavefront moved (they would add zeros)
+    const bool row_moved = __ballot(moved_bits != 0) != 0;
+    wave_moved |= row_moved;
     const int ei = I * RB + li;
     const int lo = ei + 1 > J * CB ? ei + 1 : J * CB;
     const int hi = b.E < J * CB + CB ? b.E : J * CB + CB;
     float cnt = (float)(hi > lo ? hi - lo : 0);
     float ms[3] = {0.f, 0.f, 0.f};
-    if (wave_moved) {
+    if (row_moved) {
 #pragma unroll
-      for (int s = 0; s < 3; ++s) ms[s] = admmi::row16_sum(rs[k][s]);
-      cnt -= admmi::row16_sum(rmc[k]);
+      for (int s = 0; s < 3; ++s) ms[s] = admmi::row16_sum(rs[s]);
+      cnt -= admmi::row16_sum(rmc);
     }
     if (drow[k] >= 0) {
       const float m = cq == 0 ? ms[0] : (cq == 1 ? ms[1] : ms[2]);
@@ -840,6 +848,7 @@ __device__ __forceinline__ void xpass_pair_sparse(const XArgs<float>& a, const B
       }
     }
   }
+  *flagp = (uint16_t)((SAVE && !TW) ? 0xFFFFu : movedall);
   // column partials
   if (wave_moved && lane == 0) any5 = 1;
   __syncthreads();
@@ -1591,15 +1600,17 @@ enum Features : int {
   FT_PAIR = 1,     // dense pair tiles
   FT_UHINGE = 2,   // shared-variable hinge, d <= 32
   FT_GEN = 4,      // non-overlap/wall on arbitrary variables, separable slots
-  FT_WIDE = 8,     // hinge with d <= 64, general hinge, linear dynamics
+  FT_WIDE = 8,     // general hinge with d <= 32, linear dynamics
   FT_PAIRSP = 16,  // dense pair tiles with sparse pair state
   FT_XWIDE = 32,   // hinge and margin with 64 < d < NT (two sweeps, no register arrays)
   FT_TWA = 64,     // three-weight variant (packing graphs: pair tiles, constraints, slots)
+  FT_W64 = 128,    // hinge (shared-variable or general) with 32 < d <= 64
 };
 constexpr int FS_PAIR = FT_PAIR | FT_GEN;
 constexpr int FS_PAIRSP = FT_PAIRSP | FT_GEN;
 constexpr int FS_HINGE = FT_UHINGE | FT_GEN;
-constexpr int FS_ALL = FT_PAIR | FT_UHINGE | FT_GEN | FT_WIDE | FT_PAIRSP;
+constexpr int FS_WIDE = FT_UHINGE | FT_GEN | FT_WIDE;
+constexpr int FS_ALL = FT_PAIR | FT_UHINGE | FT_GEN | FT_WIDE | FT_PAIRSP | FT_W64;
 constexpr int FS_XW = FT_XWIDE | FT_GEN;
 constexpr int FS_PAIRSP_TW = FT_PAIRSP | FT_GEN | FT_TWA;
 constexpr int FS_GEN_TW = FT_GEN | FT_TWA;
@@ -1643,10 +1654,10 @@ __device__ __forceinline__ void xpass_block(XArgs<T> a, int blk) {
       else
         xpass_pair<T, A1, MODE, 64>(a, b, local);
     }
-  } else if ((FS & (FT_UHINGE | FT_WIDE | FT_XWIDE)) && b.mode == BM_UNIF_HINGE) {
+  } else if ((FS & (FT_UHINGE | FT_W64 | FT_XWIDE)) && b.mode == BM_UNIF_HINGE) {
     if ((FS & FT_UHINGE) && b.dmax == 32)
       xpass_hinge2<T, A1, MODE>(a, b, local);
-    else if ((FS & FT_WIDE) && b.dmax == 64)
+    else if ((FS & FT_W64) && b.dmax == 64)
       xpass_hinge<T, A1, MODE, true, 64>(a, b, local);
     else if ((FS & FT_XWIDE) && b.dmax == 0)
       xpass_hinge_wide<T, A1, MODE, true>(a, b, local);
@@ -1656,15 +1667,13 @@ __device__ __forceinline__ void xpass_block(XArgs<T> a, int blk) {
     xpass_geom<T, A1, MODE, TW>(a, b, local);
   } else if ((FS & FT_XWIDE) && (b.kind == KD_HINGE || b.kind == KD_MARGIN) && b.dmax == 0) {
     xpass_hinge_wide<T, A1, MODE, false>(a, b, local);
+  } else if ((FS & FT_W64) && (b.kind == KD_HINGE || b.kind == KD_MARGIN) && b.dmax == 64) {
+    xpass_hinge<T, A1, MODE, false, 64>(a, b, local);
   } else if (FS & FT_WIDE) {
-    if (b.kind == KD_HINGE || b.kind == KD_MARGIN) {
-      if (b.dmax == 32)
-        xpass_hinge<T, A1, MODE, false, 32>(a, b, local);
-      else
-        xpass_hinge<T, A1, MODE, false, 64>(a, b, local);
-    } else {
+    if (b.kind == KD_HINGE || b.kind == KD_MARGIN)
+      xpass_hinge<T, A1, MODE, false, 32>(a, b, local);
+    else
       xpass_lindyn<T, A1, MODE>(a, b, local);
-    }
   }
 }
 
@@ -1952,7 +1961,7 @@ __global__ __launch_bounds__(NT) void zpass_kernel(ZArgs<T> a) {
 // The bucket table is staged in LDS too.  Pair tiles are not used here.
 // ---------------------------------------------------------------------------
 constexpr int RES_MAX_REG = 16;
-constexpr int FS_RES = FT_UHINGE | FT_GEN | FT_WIDE | FT_XWIDE;
+constexpr int FS_RES = FT_UHINGE | FT_GEN | FT_WIDE | FT_XWIDE | FT_W64;
 
 struct ResRegion {
   const void* src;  // global source
