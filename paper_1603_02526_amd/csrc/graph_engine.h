@@ -25,6 +25,7 @@ struct Engine : EngineBase {
   T alpha = T(1), inv_rho = T(1);
   int nb = 0;
   int fs = FS_ALL;  // x-pass feature set
+  BTab btab{};      // the bucket table as a kernel argument (first XB_INLINE buckets)
   int64_t xblocks = 0, zblocks = 0, nb_w = 0, n_w = 0, n_l = 0, n_slots = 0, nz = 0, xdelta = 0;
   int64_t n_b = 0;
   int64_t w_stride = 0, w_base = 0, l_base = 0;
@@ -223,6 +224,8 @@ struct Engine : EngineBase {
           n_twb += b.n;
       }
       if ((s = put(&bt, btc))) return s;
+      btab = BTab{};
+      for (size_t i = 0; i < btc.size() && i < (size_t)XB_INLINE; ++i) btab.d[i] = btc[i];
     }
     if ((s = alloc(&z[0], nz))) return s;
     if ((s = alloc(&z[1], nz))) return s;
@@ -321,12 +324,12 @@ struct Engine : EngineBase {
   // kernel's own begin and end (hipExtLaunchKernelGGL), used for timing.
   // Plain launches (also what stream capture records) unless an event pair
   // is asked for.
-  template <typename K, typename A>
-  static void launch(K kern, dim3 g, hipStream_t st, hipEvent_t e0, hipEvent_t e1, const A& a) {
+  template <typename K, typename... A>
+  static void launch(K kern, dim3 g, hipStream_t st, hipEvent_t e0, hipEvent_t e1, const A&... a) {
     if (e0 || e1)
-      hipExtLaunchKernelGGL(kern, g, dim3(NT), 0, st, e0, e1, 0, a);
+      hipExtLaunchKernelGGL(kern, g, dim3(NT), 0, st, e0, e1, 0, a...);
     else
-      hipLaunchKernelGGL(kern, g, dim3(NT), 0, st, a);
+      hipLaunchKernelGGL(kern, g, dim3(NT), 0, st, a...);
   }
 
   template <bool A1, int FS>
@@ -334,11 +337,11 @@ struct Engine : EngineBase {
     XArgs<T> a = xargs();
     const dim3 g((unsigned)xblocks);
     if (mode == PM_NORMAL)
-      launch(xpass_kernel<T, A1, PM_NORMAL, FS>, g, st, e0, e1, a);
+      launch(xpass_kernel<T, A1, PM_NORMAL, FS>, g, st, e0, e1, a, btab);
     else if (mode == PM_SAVE)
-      launch(xpass_kernel<T, A1, PM_SAVE, FS>, g, st, e0, e1, a);
+      launch(xpass_kernel<T, A1, PM_SAVE, FS>, g, st, e0, e1, a, btab);
     else
-      launch(xpass_kernel<T, A1, PM_RESID, FS>, g, st, e0, e1, a);
+      launch(xpass_kernel<T, A1, PM_RESID, FS>, g, st, e0, e1, a, btab);
   }
 
   template <bool A1>

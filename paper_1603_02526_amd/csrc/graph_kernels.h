@@ -1616,14 +1616,29 @@ constexpr int FS_PAIRSP_TW = FT_PAIRSP | FT_GEN | FT_TWA;
 constexpr int FS_GEN_TW = FT_GEN | FT_TWA;
 constexpr int FS_ALLX = FS_ALL | FT_XWIDE;
 
-// One x-pass workgroup's work; blk indexes the x-pass blocks of all buckets.
-template <typename T, bool A1, int MODE, int FS>
-__device__ __forceinline__ void xpass_block(XArgs<T> a, int blk) {
-  constexpr bool TW = (FS & FT_TWA) != 0;
-  a.blockmax += blk;
+// The bucket of x-pass block blk, from the table in memory.
+template <typename T>
+__device__ __forceinline__ BucketDesc find_bucket(const XArgs<T>& a, int blk) {
   int bi = 0;
   while (bi + 1 < a.nb && blk >= a.bt[bi].blk1) ++bi;
-  const BucketDesc b = a.bt[bi];
+  return a.bt[bi];
+}
+
+// Bucket table passed in the kernel arguments when a graph has at most
+// XB_INLINE buckets: a workgroup then finds its bucket in the argument
+// segment, read together with the other arguments, instead of through two
+// dependent loads from memory before its first data load.
+constexpr int XB_INLINE = 8;
+struct BTab {
+  BucketDesc d[XB_INLINE];
+};
+
+// One x-pass workgroup's work; blk indexes the x-pass blocks of all
+// buckets, b is the bucket that holds it.
+template <typename T, bool A1, int MODE, int FS>
+__device__ __forceinline__ void xpass_block(XArgs<T> a, int blk, const BucketDesc& b) {
+  constexpr bool TW = (FS & FT_TWA) != 0;
+  a.blockmax += blk;
   const int local = blk - b.blk0;
   if ((FS & (FT_PAIR | FT_PAIRSP)) && b.mode == BM_PAIR) {
     if constexpr (sizeof(T) == 4 && A1) {
@@ -1678,8 +1693,17 @@ __device__ __forceinline__ void xpass_block(XArgs<T> a, int blk) {
 }
 
 template <typename T, bool A1, int MODE, int FS>
-__global__ __launch_bounds__(NT) void xpass_kernel(XArgs<T> a) {
-  xpass_block<T, A1, MODE, FS>(a, blockIdx.x);
+__global__ __launch_bounds__(NT) void xpass_kernel(XArgs<T> a, BTab tab) {
+  const int blk = blockIdx.x;
+  BucketDesc b;
+  if (a.nb <= XB_INLINE) {
+    int bi = 0;
+    while (bi + 1 < a.nb && blk >= tab.d[bi].blk1) ++bi;
+    b = tab.d[bi];
+  } else {
+    b = find_bucket(a, blk);
+  }
+  xpass_block<T, A1, MODE, FS>(a, blk, b);
 }
 
 // z_b = sum(contributions) / deg(b), contributions read from one contiguous
@@ -2013,9 +2037,9 @@ __global__ __launch_bounds__(NT) void resident_kernel(XArgs<T> xa, ZArgs<T> za, 
     xa.z = (const T*)(lds_img + zoff[zc]);
     for (int b = 0; b < r.xblocks; ++b) {
       if (A1 && last)
-        xpass_block<T, A1, PM_SAVE, FS_RES>(xa, b);
+        xpass_block<T, A1, PM_SAVE, FS_RES>(xa, b, find_bucket(xa, b));
       else
-        xpass_block<T, A1, PM_NORMAL, FS_RES>(xa, b);
+        xpass_block<T, A1, PM_NORMAL, FS_RES>(xa, b, find_bucket(xa, b));
       __syncthreads();
     }
     za.zin = (const T*)(lds_img + zoff[zc]);
@@ -2029,7 +2053,7 @@ __global__ __launch_bounds__(NT) void resident_kernel(XArgs<T> xa, ZArgs<T> za, 
   }
   xa.z = (const T*)(lds_img + zoff[zc]);
   for (int b = 0; b < r.xblocks; ++b) {
-    xpass_block<T, A1, PM_RESID, FS_RES>(xa, b);
+    xpass_block<T, A1, PM_RESID, FS_RES>(xa, b, find_bucket(xa, b));
     __syncthreads();
   }
   for (int q = 0; q < r.nreg; ++q) {
