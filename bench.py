@@ -98,6 +98,27 @@ def time_solve(g, z0, iters, steps, warmup, torch, stream):
     return tot / steps
 
 
+def copy_floor(torch, nbytes, reps=50):
+    """Average duration of a plain device copy that reads and writes nbytes
+    in total (nbytes/2 each way), back to back on the current stream: the
+    bandwidth a streaming kernel of this size reaches in practice (launch
+    and ramp included), beside the 8 TB/s peak."""
+    n = max(1, int(nbytes) // 8)
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    us = e0.elapsed_time(e1) * 1e3 / reps
+    return dict(bytes=8 * n, us=round(us, 3), GBs=round(8 * n / (us * 1e-6) / 1e9, 1))
+
+
 def cpu_baseline(problem, iters, openmp=False, region=False):
     """The FP64 oracle on the host: serial, or its OpenMP build (threads from
     OMP_NUM_THREADS, else up to 16) with one parallel loop per update (the
@@ -546,6 +567,7 @@ def main():
     if traffic is None:
         roofline["note"] = ("no counter summary for the current kernel source: "
                             "achieved and frac need profiles/xpass_traffic.json re-taken")
+    roofline["copy_same_bytes"] = copy_floor(torch, traffic or info["algo_bytes_per_iter"])
 
     out = dict(metric="edge-updates/s", value=value, unit="edge-updates/s",
                n_gpus=1, steps=args.steps, warmup=args.warmup,
@@ -583,7 +605,8 @@ def main():
         secd["svm_100k_d20"] = dict(edge_updates_per_s=p2.n_edges * 500 / s2,
                                     ms_per_solve=s2 * 1e3, iterations=500,
                                     xpass_avg_us=x2 * 1e3 / 500,
-                                    xpass_GBs=inf2["algo_bytes_per_iter"] / (x2 * 1e-3 / 500) / 1e9)
+                                    xpass_GBs=inf2["algo_bytes_per_iter"] / (x2 * 1e-3 / 500) / 1e9,
+                                    copy_same_bytes=copy_floor(torch, inf2["algo_bytes_per_iter"]))
         # the paper's own SVM graph on the same data: a copy of w per point
         # tied by equality factors, margin and minimal-error factors
         p3 = W.svm_copies(100_000, 20, seed=1002)

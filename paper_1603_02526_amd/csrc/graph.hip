@@ -370,6 +370,16 @@ admm_status build_plan(admm_graph& g, Plan& P, bool no_tiles) {
         b.ent_aff = aff ? 1 : 0;
         b.ent_base = aff ? ezc[0] : 0;
       }
+      {
+        // the kernels compute (I, J) when the tiles are the whole upper
+        // triangle in row-major order
+        bool tri = RB == CB && b.n == (int64_t)NBC * (NBC + 1) / 2;
+        for (int64_t t = 0, I = 0, J = 0; tri && t < b.n; ++t) {
+          tri = tI[t] == I && tJ[t] == J;
+          if (++J == NBC) J = ++I;
+        }
+        b.tri = tri ? 1 : 0;
+      }
       b.sparse = (g.precision == ADMM_FP32 && P.alpha_one &&
                   g.pair_state != ADMM_PAIR_STATE_DENSE) ? 1 : 0;
       b.flag0 = P.n_flags;

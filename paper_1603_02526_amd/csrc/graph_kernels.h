@@ -60,7 +60,8 @@ struct BucketDesc {
   int32_t ent_base;
   int32_t ub;           // hinge/margin: the b edge is one variable for every factor
                         // of the bucket, which takes one partial sum per workgroup
-  int32_t ub_pad;
+  int32_t tri;          // pair layout: 64-row tiles in row-major order of the whole
+                        // upper triangle (J >= I), so (I, J) follows from the tile index
   int64_t m_off, x_off;  // element offsets of the state regions in the pool
   int64_t twb_off;      // three-weight variant: first byte of this bucket's active flags
   int64_t dst_off;      // index-buffer offset of the contribution destinations
@@ -251,6 +252,28 @@ __device__ __forceinline__ bool prox_wall_free(T* v, T qx, T qy, T qv, unsigned 
   return true;
 }
 
+// Row and column block of pair tile `tile`: computed when the tiles are the
+// whole upper triangle in row-major order (row I holds NB - I tiles and
+// starts at tile I NB - I (I - 1) / 2; a root estimate, then exact integer
+// steps), else read from the tile list.  Uniform across the workgroup.
+__device__ __forceinline__ void pair_tile(const BucketDesc& b, const int32_t* tiles, int tile,
+                                          int& I, int& J) {
+  if (b.tri) {
+    const int nb = b.NB;
+    const float q = (float)(2 * nb + 1);
+    int i = (int)(0.5f * (q - sqrtf(q * q - 8.f * (float)tile)));
+    i = i < 0 ? 0 : (i > nb - 1 ? nb - 1 : i);
+    auto first = [nb](int r) { return r * nb - r * (r - 1) / 2; };
+    while (i + 1 < nb && first(i + 1) <= tile) ++i;
+    while (i > 0 && first(i) > tile) --i;
+    I = i;
+    J = i + (tile - first(i));
+  } else {
+    I = tiles[2 * tile];
+    J = tiles[2 * tile + 1];
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Dense pairwise non-overlap tiles.  Tile (I, J) holds the pairs
 // (e_i, e_j) = (I*RB + li, J*64 + lj), li < RB, lj < 64, of which those with
@@ -272,7 +295,8 @@ __device__ __forceinline__ void xpass_pair(const XArgs<T>& a, const BucketDesc& 
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int32_t* tiles = a.idx + b.idx_off;
   const int32_t* ent = tiles + 2 * b.n;
-  const int I = tiles[2 * tile], J = tiles[2 * tile + 1];
+  int I, J;
+  pair_tile(b, tiles, tile, I, J);
   if (t < RB + CB) {
     const bool isrow = t < RB;
     const int l = isrow ? t : t - RB;
@@ -451,7 +475,8 @@ __device__ __forceinline__ void xpass_pair_v4(const XArgs<float>& a, const Bucke
   const int rg = lane >> 4, cq = lane & 15;
   const int32_t* tiles = a.idx + b.idx_off;
   const int32_t* ent = tiles + 2 * b.n;
-  const int I = tiles[2 * tile], J = tiles[2 * tile + 1];
+  int I, J;
+  pair_tile(b, tiles, tile, I, J);
   constexpr int64_t TS = 6 * (int64_t)TSZ;
   const float* src = a.pool + (MODE == PM_RESID ? b.x_off : b.m_off) + (int64_t)tile * TS;
   f4v mv[PRT][6];
@@ -635,7 +660,8 @@ __device__ __forceinline__ void xpass_pair_sparse(const XArgs<float>& a, const B
   const int rg = lane >> 4, cq = lane & 15;
   const int32_t* tiles = a.idx + b.idx_off;
   const int32_t* ent = tiles + 2 * b.n;
-  const int I = tiles[2 * tile], J = tiles[2 * tile + 1];
+  int I, J;
+  pair_tile(b, tiles, tile, I, J);
   constexpr int64_t TS = 6 * (int64_t)TSZ;
   uint16_t* flagp = a.flags + b.flag0 + (int64_t)tile * NT + t;
   const uint32_t fl = *flagp;       // set: m of the pair is stored
