@@ -319,6 +319,7 @@ admm_status build_plan(admm_graph& g, Plan& P, bool no_tiles) {
     b.kind = gr.kind;
     b.arity = gr.arity;
     b.idx_off = (int64_t)P.idx.size();
+    P.par.resize((size_t)round_up((int64_t)P.par.size(), 4), 0.0);  // 16-byte aligned rows
     b.par_off = (int64_t)P.par.size();
     P.n_m = round_up(P.n_m, 64);  // every bucket's state starts 256-byte aligned
     b.m_off = P.n_m;
@@ -458,7 +459,11 @@ admm_status build_plan(admm_graph& g, Plan& P, bool no_tiles) {
       b.d = gr.arity - 1;
       b.dmax = hinge_dmax(b.d);
       b.n = gr.n;
-      b.nfp = round_up(gr.n, 64);
+      // d < 32: four lanes per four factors in FP32 with alpha = 1 (NT
+      // factors per workgroup, rows padded to whole workgroups so that every
+      // 16-byte access stays in its row), else two lanes per factor (NT / 2)
+      b.quad = (b.dmax == 32 && b.d < 32 && g.precision == ADMM_FP32 && P.alpha_one) ? 1 : 0;
+      b.nfp = round_up(gr.n, b.quad ? NT : 64);
       b.nslot = gr.arity;
       for (int e = 0; e < gr.arity; ++e) P.idx.push_back((int32_t)zof(0, e));
       const int d = b.d;
@@ -474,8 +479,7 @@ admm_status build_plan(admm_graph& g, Plan& P, bool no_tiles) {
         par[(d + 2) * b.nfp + f] = rg / (aa + 1.0);
       }
       P.n_m += (int64_t)gr.arity * b.nfp;
-      // d <= 32: two lanes per factor, NT / 2 factors per workgroup
-      const int64_t fpb = b.dmax == 32 ? NT / 2 : NT;
+      const int64_t fpb = b.quad ? NT : (b.dmax == 32 ? NT / 2 : NT);
       const int64_t tiles = (gr.n + fpb - 1) / fpb;
       b.dst_off = (int64_t)P.idx.size();
       P.idx.resize(P.idx.size() + tiles * gr.arity, -1);

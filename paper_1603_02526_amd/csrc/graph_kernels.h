@@ -62,6 +62,8 @@ struct BucketDesc {
                         // of the bucket, which takes one partial sum per workgroup
   int32_t tri;          // pair layout: 64-row tiles in row-major order of the whole
                         // upper triangle (J >= I), so (I, J) follows from the tile index
+  int32_t quad;         // shared-variable hinge: four factors per lane (FP32, alpha = 1)
+  int32_t quad_pad;
   int64_t m_off, x_off;  // element offsets of the state regions in the pool
   int64_t twb_off;      // three-weight variant: first byte of this bucket's active flags
   int64_t dst_off;      // index-buffer offset of the contribution destinations
@@ -1068,9 +1070,8 @@ __device__ __forceinline__ double sum_parity_row<double>(double v) {
   return v;
 }
 
-template <typename T, bool A1, int MODE>
+template <typename T, bool A1, int MODE, int DH>
 __device__ __forceinline__ void xpass_hinge2(const XArgs<T>& a, const BucketDesc& b, int blk) {
-  constexpr int DH = 16;
   constexpr int FPB = NT / 2;
   __shared__ T wsum2[NT / 16][33];   // per 16-lane row, per component
   __shared__ T zsh[33];              // z of the bucket's d + 1 variables
@@ -1168,6 +1169,129 @@ __device__ __forceinline__ void xpass_hinge2(const XArgs<T>& a, const BucketDesc
       T acc = wsum2[0][t];
 #pragma unroll
       for (int q = 1; q < NT / 16; ++q) acc += wsum2[q][t];
+      a.pool[a.idx[b.dst_off + (int64_t)blk * (d + 1) + t]] = acc;
+    }
+  }
+}
+
+// Shared-variable hinge with d < 32, FP32 and alpha = 1: each group of
+// four lanes takes four consecutive factors, so that every load and store
+// of a lane is 16 bytes (four factors' values of one edge).  Lane q of a
+// group takes the edges [q DQ, (q + 1) DQ) of the d + 1 (the b edge last,
+// its parameter y); its partial dot products of the four factors are added
+// over the group in a fixed order, so all four lanes hold the same bits.
+// The edges' m are summed over the workgroup's factors: over a lane's four
+// factors, over the lanes of the same q in each 16-lane row (DPP), across
+// the rows, then across the wavefronts in order.  NT factors per workgroup.
+__device__ __forceinline__ float quad_sum4(float v) {
+  // (v0 + v1) + (v2 + v3) of the group's four lanes, the same in each
+  const float v0 = ADMM_DPP(v, 0x00, 0xF), v1 = ADMM_DPP(v, 0x55, 0xF);
+  const float v2 = ADMM_DPP(v, 0xAA, 0xF), v3 = ADMM_DPP(v, 0xFF, 0xF);
+  return (v0 + v1) + (v2 + v3);
+}
+
+template <bool A1, int MODE, int DQ>
+__device__ __forceinline__ void xpass_hinge4(const XArgs<float>& a, const BucketDesc& b, int blk) {
+  __shared__ float wsum4[NT / 64][33];
+  __shared__ float zsh4[33];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6, q = t & 3;
+  const int d = b.d;
+  const int64_t f0 = (int64_t)blk * NT + 4 * (t >> 2);   // the group's first factor
+  const int64_t nfp = b.nfp;
+  const int32_t* zo = a.idx + b.idx_off;
+  const float* P = a.par + b.par_off;
+  float* M = a.pool + b.m_off;
+  float* X = a.pool + b.x_off;
+  const int k0 = q * DQ;
+  if (t <= d) zsh4[t] = a.z[zo[t]];
+  // loads first: the lane's edges (an edge index past d reads edge d) and
+  // the four factors' y, C and rho / (|a|^2 + 1)
+  f4v mv[DQ], pv[DQ];
+#pragma unroll
+  for (int i = 0; i < DQ; ++i) {
+    const int k = k0 + i <= d ? k0 + i : d;
+    if constexpr (MODE == PM_RESID) {
+      mv[i] = *(const f4v*)(X + k * nfp + f0);
+    } else {
+      mv[i] = *(const f4v*)(M + k * nfp + f0);
+      pv[i] = *(const f4v*)(P + k * nfp + f0);
+    }
+  }
+  f4v C4 = {0.f, 0.f, 0.f, 0.f}, iD4 = C4;
+  if constexpr (MODE != PM_RESID) {
+    C4 = *(const f4v*)(P + (d + 1) * nfp + f0);
+    iD4 = *(const f4v*)(P + (d + 2) * nfp + f0);
+  }
+  __syncthreads();
+  bool valid[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) valid[j] = f0 + j < b.n;
+  if constexpr (MODE == PM_RESID) {
+    float rmax = 0.f;
+#pragma unroll
+    for (int i = 0; i < DQ; ++i) {
+      const int k = k0 + i;
+      if (k <= d) {
+        const float zk = zsh4[k];
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          if (valid[j]) rmax = tmax(rmax, tabs(mv[i][j] - zk));
+      }
+    }
+    block_max_store(rmax, a.blockmax);
+    return;
+  } else {
+    // u = m - z, n = z - u; partial dot products of the lane's edges
+    f4v dot = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int i = 0; i < DQ; ++i) {
+      const int k = k0 + i;
+      const float zk = zsh4[k <= d ? k : d];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const float u = mv[i][j] - zk;
+        const float n = zk - u;
+        mv[i][j] = u;          // mv holds u from here on
+        pv[i][j] = k <= d ? pv[i][j] : 0.f;
+        dot[j] += n * pv[i][j];
+      }
+    }
+    f4v st;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const float full = quad_sum4(dot[j]);
+      const float tau = tmin(C4[j], tmax(0.f, (1.f - full) * iD4[j]));
+      st[j] = tau * (float)b.irho;
+    }
+    // x = n + st p, m = x + u; the edges' sums over the workgroup's factors
+#pragma unroll
+    for (int i = 0; i < DQ; ++i) {
+      const int k = k0 + i;
+      const float zk = zsh4[k <= d ? k : d];
+      f4v mn, xk;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const float u = mv[i][j];
+        xk[j] = (zk - u) + st[j] * pv[i][j];
+        mn[j] = xk[j] + u;
+      }
+      if (k <= d) {
+        *(f4v*)(M + k * nfp + f0) = mn;
+        if constexpr (MODE == PM_SAVE) *(f4v*)(X + k * nfp + f0) = xk;
+      }
+      float sv = ((valid[0] ? mn[0] : 0.f) + (valid[1] ? mn[1] : 0.f)) +
+                 ((valid[2] ? mn[2] : 0.f) + (valid[3] ? mn[3] : 0.f));
+      sv += ADMM_DPP(sv, 0x124, 0xF);   // row_ror:4
+      sv += ADMM_DPP(sv, 0x128, 0xF);   // row_ror:8
+      sv += __shfl_xor(sv, 16, 64);
+      sv += __shfl_xor(sv, 32, 64);
+      if (lane < 4 && k <= d) wsum4[w][k] = sv;
+    }
+    __syncthreads();
+    if (t <= d) {
+      float acc = wsum4[0][t];
+#pragma unroll
+      for (int r = 1; r < NT / 64; ++r) acc += wsum4[r][t];
       a.pool[a.idx[b.dst_off + (int64_t)blk * (d + 1) + t]] = acc;
     }
   }
@@ -1696,8 +1820,32 @@ __device__ __forceinline__ void xpass_block(XArgs<T> a, int blk, const BucketDes
         xpass_pair<T, A1, MODE, 64>(a, b, local);
     }
   } else if ((FS & (FT_UHINGE | FT_W64 | FT_XWIDE)) && b.mode == BM_UNIF_HINGE) {
-    if ((FS & FT_UHINGE) && b.dmax == 32)
-      xpass_hinge2<T, A1, MODE>(a, b, local);
+    if ((FS & FT_UHINGE) && b.dmax == 32 && b.quad) {
+      if constexpr (sizeof(T) == 4 && A1) {
+        // four lanes per four factors, ceil((d + 1) / 4) <= 8 edges per lane
+        const int dq = (b.d + 4) / 4;
+        if (dq <= 2)
+          xpass_hinge4<A1, MODE, 2>(a, b, local);
+        else if (dq <= 4)
+          xpass_hinge4<A1, MODE, 4>(a, b, local);
+        else if (dq <= 6)
+          xpass_hinge4<A1, MODE, 6>(a, b, local);
+        else
+          xpass_hinge4<A1, MODE, 8>(a, b, local);
+      }
+    } else if ((FS & FT_UHINGE) && b.dmax == 32) {
+      // per lane ceil(d / 2) components, register arrays sized to the next
+      // multiple of 4 (no loads of unused components)
+      const int dh = (b.d + 1) / 2;
+      if (dh <= 4)
+        xpass_hinge2<T, A1, MODE, 4>(a, b, local);
+      else if (dh <= 8)
+        xpass_hinge2<T, A1, MODE, 8>(a, b, local);
+      else if (dh <= 12)
+        xpass_hinge2<T, A1, MODE, 12>(a, b, local);
+      else
+        xpass_hinge2<T, A1, MODE, 16>(a, b, local);
+    }
     else if ((FS & FT_W64) && b.dmax == 64)
       xpass_hinge<T, A1, MODE, true, 64>(a, b, local);
     else if ((FS & FT_XWIDE) && b.dmax == 0)

@@ -123,9 +123,13 @@ def test_svm_layout():
     inf = g.info()
     assert inf["n_edges"] == 5000 * 21 + 20
     assert inf["n_pair_tiles"] == 0
-    # one partial per variable per 128-factor workgroup (two lanes per
-    # factor for d <= 32), plus 20 L2 slots
-    assert inf["n_contributions"] == 40 * 21 + 20
+    # one partial per variable per 256-factor workgroup (FP32: four lanes
+    # per four factors for d <= 32), plus 20 L2 slots
+    assert inf["n_contributions"] == 20 * 21 + 20
+    # FP64: two lanes per factor, 128 factors per workgroup
+    g = A.Graph.from_problem(p, device=None, precision=A.FP64)
+    assert _finalize_cpu(g) in (A.OK, A.E_NO_DEVICE)
+    assert g.info()["n_contributions"] == 40 * 21 + 20
 
 
 def test_copies_svm_layout():
