@@ -319,7 +319,6 @@ admm_status build_plan(admm_graph& g, Plan& P, bool no_tiles) {
     b.kind = gr.kind;
     b.arity = gr.arity;
     b.idx_off = (int64_t)P.idx.size();
-    P.par.resize((size_t)round_up((int64_t)P.par.size(), 4), 0.0);  // 16-byte aligned rows
     b.par_off = (int64_t)P.par.size();
     P.n_m = round_up(P.n_m, 64);  // every bucket's state starts 256-byte aligned
     b.m_off = P.n_m;
@@ -462,11 +461,19 @@ admm_status build_plan(admm_graph& g, Plan& P, bool no_tiles) {
       // d < 32: four lanes per four factors in FP32 with alpha = 1 (NT
       // factors per workgroup, rows padded to whole workgroups so that every
       // 16-byte access stays in its row), else two lanes per factor (NT / 2)
-      b.quad = (b.dmax == 32 && b.d < 32 && g.precision == ADMM_FP32 && P.alpha_one) ? 1 : 0;
+      // (not in a plan built for the resident driver, whose LDS image keeps
+      // the rows at their 64-factor padding)
+      b.quad = (b.dmax == 32 && b.d < 32 && g.precision == ADMM_FP32 && P.alpha_one &&
+                !P.no_tiles) ? 1 : 0;
       b.nfp = round_up(gr.n, b.quad ? NT : 64);
       b.nslot = gr.arity;
       for (int e = 0; e < gr.arity; ++e) P.idx.push_back((int32_t)zof(0, e));
       const int d = b.d;
+      if (b.quad) {
+        // 16-byte aligned parameter rows
+        P.par.resize((size_t)round_up((int64_t)P.par.size(), 4), 0.0);
+        b.par_off = (int64_t)P.par.size();
+      }
       P.par.resize(P.par.size() + (size_t)(d + 3) * b.nfp, 0.0);
       double* par = P.par.data() + b.par_off;
       for (int64_t f = 0; f < gr.n; ++f) {
