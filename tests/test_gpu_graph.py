@@ -161,6 +161,21 @@ def test_svm_parity(N, d, prec, iters, tol):
     _traj(p, iters, prec, tol)
 
 
+@pytest.mark.parametrize("d", [1, 6, 13, 24, 31, 32])
+def test_svm_four_lane_hinge(d):
+    """FP32 shared-variable hinge with four lanes per four factors: every
+    register width (2, 4, 6 and 8 edges per lane), a factor count that is not
+    a multiple of 4 or of the workgroup (1001), and d = 32, which keeps two
+    lanes per factor (one partial per variable per workgroup: 256 factors per
+    workgroup, 128 at d = 32)."""
+    p = W.svm(1001, d, seed=700 + d)
+    g = A.Graph.from_problem(p, precision=FP32, driver=A.DRIVER_LAUNCHES)
+    per_wg = 128 if d == 32 else 256
+    assert g.info()["n_contributions"] == -(-1001 // per_wg) * (d + 1) + d
+    _traj(p, 50, FP32, 1e-4, driver=A.DRIVER_LAUNCHES)
+    _one_step(p, 20, FP32, 1e-5, driver=A.DRIVER_LAUNCHES)
+
+
 @pytest.mark.parametrize("N,d,seed,prec,iters,tol", [(500, 100, 611, FP64, 50, 1e-9),
                                                      (500, 100, 611, FP32, 50, 1e-4),
                                                      (400, 200, 612, FP64, 40, 1e-9),
