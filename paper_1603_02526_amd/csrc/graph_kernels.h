@@ -1070,11 +1070,24 @@ __device__ __forceinline__ double sum_parity_row<double>(double v) {
   return v;
 }
 
+// LDS of the shared-variable hinge paths, one allocation per precision
+// whatever the register width they are instantiated for.
+template <typename T>
+struct HingeSmem {
+  T wsum[NT / 16][33];   // per 16-lane row (or per wavefront), per component
+  T zsh[33];             // z of the bucket's d + 1 variables
+};
+template <typename T>
+__device__ __forceinline__ HingeSmem<T>& hinge_smem() {
+  __shared__ HingeSmem<T> sm;
+  return sm;
+}
+
 template <typename T, bool A1, int MODE, int DH>
 __device__ __forceinline__ void xpass_hinge2(const XArgs<T>& a, const BucketDesc& b, int blk) {
   constexpr int FPB = NT / 2;
-  __shared__ T wsum2[NT / 16][33];   // per 16-lane row, per component
-  __shared__ T zsh[33];              // z of the bucket's d + 1 variables
+  auto& wsum2 = hinge_smem<T>().wsum;
+  auto& zsh = hinge_smem<T>().zsh;
   const int t = threadIdx.x, lane = t & 63, h = t & 1, row = t >> 4;
   const int d = b.d, dh = (d + 1) / 2;
   const int64_t f = (int64_t)blk * FPB + (t >> 1);
@@ -1192,8 +1205,8 @@ __device__ __forceinline__ float quad_sum4(float v) {
 
 template <bool A1, int MODE, int DQ>
 __device__ __forceinline__ void xpass_hinge4(const XArgs<float>& a, const BucketDesc& b, int blk) {
-  __shared__ float wsum4[NT / 64][33];
-  __shared__ float zsh4[33];
+  auto& wsum4 = hinge_smem<float>().wsum;   // rows 0 .. NT / 64 - 1 used
+  auto& zsh4 = hinge_smem<float>().zsh;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6, q = t & 3;
   const int d = b.d;
   const int64_t f0 = (int64_t)blk * NT + 4 * (t >> 2);   // the group's first factor

@@ -450,7 +450,12 @@ def test_resident_driver_alpha_and_u0_fp64(alpha):
 
 @pytest.mark.parametrize("name", ["svm_300_d3", "mpc_T12"])
 def test_resident_matches_launches(name):
-    """Without pair tiles both drivers run the same plan: same iterates."""
+    """Without pair tiles both drivers run the same arithmetic: the same
+    iterates up to the order of the per-workgroup sums (the FP32 SVM's
+    hinge takes two lanes per factor in a resident plan and four lanes per
+    four factors otherwise).  Residuals are maxima of differences of
+    z-sized values, so their error is bounded by the iterates' error times
+    the size of z."""
     p = _small_cases()[name]
     for prec, tol in ((FP64, 1e-13), (FP32, 1e-6)):
         a = A.Graph.from_problem(p, precision=prec, driver=A.DRIVER_RESIDENT)
@@ -460,8 +465,9 @@ def test_resident_matches_launches(name):
         a.run(40)
         b.run(40)
         assert rel(a.z(), b.z()) <= tol and rel(a.u(), b.u()) <= tol and rel(a.x(), b.x()) <= tol
-        ra, rb_ = a.residuals(), b.residuals()
-        assert np.allclose(ra, rb_, rtol=1e-6, atol=1e-12)
+        zmax = float(np.max(np.abs(b.z()))) + 1.0
+        for ra, rb_ in zip(a.residuals(), b.residuals()):
+            assert abs(ra - rb_) <= 4 * tol * zmax, (ra, rb_)
 
 
 def test_resident_determinism_resume_and_profiled():
