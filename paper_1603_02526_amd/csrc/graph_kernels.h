@@ -1917,6 +1917,14 @@ __device__ __forceinline__ void zpass_tlist(const ZArgs<T>& a, int blk, T& dmax)
   const int kk = threadIdx.x & (L - 1), q = threadIdx.x / L;
   const int64_t k = (int64_t)blk * L + kk;
   const bool ok = k < a.n_t;
+  // the list's z index and degree, read with the contributions (not after
+  // the reduction's barrier)
+  int zi = 0;
+  T dg = T(1);
+  if (ok && q == 0) {
+    zi = a.var_t[k];
+    if (!TW) dg = a.deg_t[k];
+  }
   T num = T(0), den = T(0);
   if (ok) {
     const T* p = a.pool + a.t_base + k;
@@ -1960,13 +1968,12 @@ __device__ __forceinline__ void zpass_tlist(const ZArgs<T>& a, int blk, T& dmax)
       tn += zt[0][i * L + kk];
       td += zt[1][i * L + kk];
     }
-    const int zi = a.var_t[k];
     T zn = a.zin[zi];
     if (TW) {
       if (td > T(0)) zn = tn / td;
       a.zfree[zi] = td > T(0) ? 0 : 1;
     } else {
-      zn = tn / a.deg_t[k];
+      zn = tn / dg;
     }
     a.zout[zi] = zn;
     if (a.check) dmax = tabs(zn - a.zin[zi]) * ((!TW && a.rmz) ? a.rmz[zi] : T(1));
@@ -2074,6 +2081,8 @@ __device__ __forceinline__ void zpass_block(ZArgs<T> a, int blk) {
   T dmax = T(0);
   if (blk < a.n_b) {
     const int64_t o1 = a.rng_b[2 * blk + 1];
+    const int zi = a.var_b[blk];       // read before the reduction
+    const T dg = a.deg_b[blk];
     T s = T(0);
     if (a.wz) {
       for (int64_t j = a.rng_b[2 * blk] + threadIdx.x; j < o1; j += NT) s += a.wz[j] * a.pool[j];
@@ -2087,8 +2096,7 @@ __device__ __forceinline__ void zpass_block(ZArgs<T> a, int blk) {
       T t = zred[0];
 #pragma unroll
       for (int q = 1; q < NT / 64; ++q) t += zred[q];
-      const int zi = a.var_b[blk];
-      const T zn = t / a.deg_b[blk];
+      const T zn = t / dg;
       a.zout[zi] = zn;
       if (a.check) dmax = tabs(zn - a.zin[zi]) * (a.rmz ? a.rmz[zi] : T(1));
     }
@@ -2096,6 +2104,8 @@ __device__ __forceinline__ void zpass_block(ZArgs<T> a, int blk) {
     const int sl = threadIdx.x & (ZSEG - 1);
     const int64_t k = (int64_t)(blk - a.n_b) * ZPB + (threadIdx.x / ZSEG);
     const bool ok = k < a.n_w;
+    const int zi = ok ? a.var_w[k] : 0;   // read with the contributions
+    const T dg = ok ? a.deg_w[k] : T(1);
     T s = T(0);
     if (ok) {
       if (a.w_stride) {
@@ -2126,8 +2136,7 @@ __device__ __forceinline__ void zpass_block(ZArgs<T> a, int blk) {
     }
     s = admmi::row16_sum(s);
     if (ok && sl == 0) {
-      const int zi = a.var_w[k];
-      const T zn = s / a.deg_w[k];
+      const T zn = s / dg;
       a.zout[zi] = zn;
       if (a.check) dmax = tabs(zn - a.zin[zi]) * (a.rmz ? a.rmz[zi] : T(1));
     }
@@ -2148,8 +2157,11 @@ __device__ __forceinline__ void zpass_block(ZArgs<T> a, int blk) {
 #pragma unroll
         for (int j = 1; j < LANE_MAX; ++j) s += p[j];
       }
-      T zn = a.zin[zi];
-      if (d > T(0)) zn = s / d;
+      T zn;
+      if (d > T(0))
+        zn = s / d;
+      else
+        zn = a.zin[zi];   // no edge: z keeps its value
       a.zout[zi] = zn;
       if (a.check) dmax = tabs(zn - a.zin[zi]) * (a.rmz ? a.rmz[zi] : T(1));
     }
