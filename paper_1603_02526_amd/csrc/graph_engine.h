@@ -181,7 +181,8 @@ struct Engine : EngineBase {
         else if (b.mode == BM_GEN_SLOT || b.kind == KD_NONOVERLAP || b.kind == KD_WALL ||
                  b.kind == KD_EQUAL)
           need |= FT_GEN;
-        else need |= FT_WIDE;
+        else if (b.kind == KD_HINGE || b.kind == KD_MARGIN) need |= FT_WIDE;
+        else need |= FT_LINDYN;
       }
       if (twa) need |= FT_TWA;
       fs = (need & FT_TWA) ? ((need & FT_PAIRSP) ? FS_PAIRSP_TW : FS_GEN_TW)
@@ -189,6 +190,7 @@ struct Engine : EngineBase {
            : ((need & ~FS_PAIRSP) == 0) ? FS_PAIRSP
            : ((need & ~FS_HINGE) == 0)  ? FS_HINGE
            : ((need & ~FS_WIDE) == 0)   ? FS_WIDE
+           : ((need & ~FS_DYN) == 0)    ? FS_DYN
            : ((need & ~FS_XW) == 0)     ? FS_XW
            : ((need & ~FS_ALL) == 0)    ? FS_ALL
                                         : FS_ALLX;
@@ -350,6 +352,7 @@ struct Engine : EngineBase {
     else if (fs == FS_PAIRSP) launch_x_fs<A1, FS_PAIRSP>(mode, st, e0, e1);
     else if (fs == FS_HINGE) launch_x_fs<A1, FS_HINGE>(mode, st, e0, e1);
     else if (fs == FS_WIDE) launch_x_fs<A1, FS_WIDE>(mode, st, e0, e1);
+    else if (fs == FS_DYN) launch_x_fs<A1, FS_DYN>(mode, st, e0, e1);
     else if (fs == FS_XW) launch_x_fs<A1, FS_XW>(mode, st, e0, e1);
     else if (fs == FS_ALL) launch_x_fs<A1, FS_ALL>(mode, st, e0, e1);
     else if (fs == FS_ALLX) launch_x_fs<A1, FS_ALLX>(mode, st, e0, e1);

@@ -1763,17 +1763,19 @@ enum Features : int {
   FT_PAIR = 1,     // dense pair tiles
   FT_UHINGE = 2,   // shared-variable hinge, d <= 32
   FT_GEN = 4,      // non-overlap/wall on arbitrary variables, separable slots
-  FT_WIDE = 8,     // general hinge with d <= 32, linear dynamics
+  FT_WIDE = 8,     // general hinge and margin with d <= 32
   FT_PAIRSP = 16,  // dense pair tiles with sparse pair state
   FT_XWIDE = 32,   // hinge and margin with 64 < d < NT (two sweeps, no register arrays)
   FT_TWA = 64,     // three-weight variant (packing graphs: pair tiles, constraints, slots)
   FT_W64 = 128,    // hinge (shared-variable or general) with 32 < d <= 64
+  FT_LINDYN = 256, // linear-dynamics projections
 };
 constexpr int FS_PAIR = FT_PAIR | FT_GEN;
 constexpr int FS_PAIRSP = FT_PAIRSP | FT_GEN;
 constexpr int FS_HINGE = FT_UHINGE | FT_GEN;
-constexpr int FS_WIDE = FT_UHINGE | FT_GEN | FT_WIDE;
-constexpr int FS_ALL = FT_PAIR | FT_UHINGE | FT_GEN | FT_WIDE | FT_PAIRSP | FT_W64;
+constexpr int FS_WIDE = FT_GEN | FT_WIDE;
+constexpr int FS_DYN = FT_GEN | FT_LINDYN;
+constexpr int FS_ALL = FT_PAIR | FT_UHINGE | FT_GEN | FT_WIDE | FT_PAIRSP | FT_W64 | FT_LINDYN;
 constexpr int FS_XW = FT_XWIDE | FT_GEN;
 constexpr int FS_PAIRSP_TW = FT_PAIRSP | FT_GEN | FT_TWA;
 constexpr int FS_GEN_TW = FT_GEN | FT_TWA;
@@ -1871,11 +1873,10 @@ __device__ __forceinline__ void xpass_block(XArgs<T> a, int blk, const BucketDes
     xpass_hinge_wide<T, A1, MODE, false>(a, b, local);
   } else if ((FS & FT_W64) && (b.kind == KD_HINGE || b.kind == KD_MARGIN) && b.dmax == 64) {
     xpass_hinge<T, A1, MODE, false, 64>(a, b, local);
-  } else if (FS & FT_WIDE) {
-    if (b.kind == KD_HINGE || b.kind == KD_MARGIN)
-      xpass_hinge<T, A1, MODE, false, 32>(a, b, local);
-    else
-      xpass_lindyn<T, A1, MODE>(a, b, local);
+  } else if ((FS & FT_WIDE) && (b.kind == KD_HINGE || b.kind == KD_MARGIN)) {
+    xpass_hinge<T, A1, MODE, false, 32>(a, b, local);
+  } else if (FS & FT_LINDYN) {
+    xpass_lindyn<T, A1, MODE>(a, b, local);
   }
 }
 
@@ -2184,7 +2185,7 @@ __global__ __launch_bounds__(NT) void zpass_kernel(ZArgs<T> a) {
 // The bucket table is staged in LDS too.  Pair tiles are not used here.
 // ---------------------------------------------------------------------------
 constexpr int RES_MAX_REG = 16;
-constexpr int FS_RES = FT_UHINGE | FT_GEN | FT_WIDE | FT_XWIDE | FT_W64;
+constexpr int FS_RES = FT_UHINGE | FT_GEN | FT_WIDE | FT_XWIDE | FT_W64 | FT_LINDYN;
 
 struct ResRegion {
   const void* src;  // global source
